@@ -1,0 +1,383 @@
+/*
+ * Sequential CPU oracle for batched SPIR-V decode, validate and encode.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously-correct
+ * reference that the GPU library is checked against.  Only the tests, the
+ * smoke check and the benchmark's CPU-baseline leg may load it.  It shares no
+ * code, header, table or constant generator with the GPU path and includes
+ * nothing from it.
+ *
+ * What it follows (Beehive SPIR-V Toolkit paper, arXiv 2305.09493):
+ *   - header fields in the standard's order, bound recomputed when the module
+ *     is written (section "SPIR-V Library", header-construction listing and
+ *     the paragraph on the initial bound);
+ *   - every instruction and operand writes its own 32-bit words and reports a
+ *     word count that sizes the module (section "Parsing Operand Kinds");
+ *   - IDs are requested once per module and each construct is assigned once,
+ *     the SSA rule (section "Enabling Function Composition", SSA paragraph);
+ *   - the disassembler turns the binary back into instructions (section
+ *     "Dis/Assembler"); the library validates modules before storing them
+ *     (section "Validation Rules").
+ * SPIR-V binary facts used: magic 0x07230203, schema word 0, first word of an
+ * instruction = (word count << 16) | opcode.  The grammar table below is this
+ * file's own copy of the twelve opcodes of the synthetic workload.
+ *
+ * Where the paper is silent the readings are: word counts are in words and
+ * include the first word; the undefined-ID rule means "defined anywhere in the
+ * module"; checks run header -> parse (first failing instruction) -> semantic
+ * (set of classes, primary code by OOB > DUP > UNDEF); at one instruction the
+ * order is count/overrun -> opcode -> fixed count -> string; the version word
+ * must have zero reserved bytes, major 1 and minor <= 6; ID 0 is invalid.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_MAGIC 0x07230203u
+
+enum {
+  ORC_OK = 0,
+  ORC_TRUNCATED_HEADER = 1,
+  ORC_BAD_MAGIC = 2,
+  ORC_BAD_VERSION = 3,
+  ORC_BAD_SCHEMA = 4,
+  ORC_BAD_WORD_COUNT = 5,
+  ORC_UNKNOWN_OPCODE = 6,
+  ORC_BAD_STRING = 7,
+  ORC_ID_OUT_OF_BOUND = 8,
+  ORC_DUPLICATE_ID = 9,
+  ORC_UNDEFINED_ID = 10,
+};
+enum {
+  ORC_ENC_OK = 0,
+  ORC_ENC_UNKNOWN_OPCODE = 1,
+  ORC_ENC_OPERAND_COUNT = 2,
+  ORC_ENC_BAD_STRING = 3,
+  ORC_ENC_TOO_LONG = 4,
+  ORC_ENC_BAD_ID = 5,
+};
+
+typedef struct {
+  uint32_t code, sem_mask, err_word, n_inst;
+} orc_result;
+
+/* One grammar entry: opcode, word count (0 = OpName: >= 3, operand then a
+ * string), and the role of each operand word after the first word:
+ * 'U' ID use, 'D' result ID, 'L' literal, 'S' string words to the end. */
+typedef struct {
+  uint16_t opcode;
+  uint16_t word_count;
+  const char *roles;
+} orc_inst;
+
+static const orc_inst GRAMMAR[] = {
+    {5, 0, "US"},     /* OpName         */
+    {14, 3, "LL"},    /* OpMemoryModel  */
+    {17, 2, "L"},     /* OpCapability   */
+    {21, 4, "DLL"},   /* OpTypeInt      */
+    {43, 4, "UDL"},   /* OpConstant     */
+    {54, 5, "UDLU"},  /* OpFunction     */
+    {56, 1, ""},      /* OpFunctionEnd  */
+    {61, 4, "UDU"},   /* OpLoad         */
+    {62, 3, "UU"},    /* OpStore        */
+    {128, 5, "UDUU"}, /* OpIAdd         */
+    {248, 2, "D"},    /* OpLabel        */
+    {253, 1, ""},     /* OpReturn       */
+};
+#define ORC_OPNAME 5u
+
+static const orc_inst *lookup(uint32_t opcode) {
+  for (size_t i = 0; i < sizeof(GRAMMAR) / sizeof(GRAMMAR[0]); ++i)
+    if (GRAMMAR[i].opcode == opcode) return &GRAMMAR[i];
+  return NULL;
+}
+
+/* A literal string is stored as bytes little-endian within each word, ends
+ * with a NUL byte, and is zero padded to a whole word.  So the first NUL must
+ * lie in the last word and every byte after it must be zero. */
+static int string_ok(const uint32_t *w, uint64_t n_words) {
+  uint64_t n_bytes = 4 * n_words;
+  uint64_t first_nul = n_bytes;
+  for (uint64_t b = 0; b < n_bytes; ++b) {
+    uint32_t byte = (w[b / 4] >> (8 * (b % 4))) & 0xFFu;
+    if (byte == 0) {
+      first_nul = b;
+      break;
+    }
+  }
+  if (first_nul == n_bytes) return 0;          /* no terminator */
+  if (first_nul / 4 != n_words - 1) return 0;  /* terminator not in the last word */
+  for (uint64_t b = first_nul; b < n_bytes; ++b)
+    if (((w[b / 4] >> (8 * (b % 4))) & 0xFFu) != 0) return 0;
+  return 1;
+}
+
+static int cmp_u32(const void *a, const void *b) {
+  uint32_t x = *(const uint32_t *)a, y = *(const uint32_t *)b;
+  return (x > y) - (x < y);
+}
+
+static int contains(const uint32_t *sorted, uint64_t n, uint32_t v) {
+  uint64_t lo = 0, hi = n;
+  while (lo < hi) {
+    uint64_t mid = lo + (hi - lo) / 2;
+    if (sorted[mid] < v) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo < n && sorted[lo] == v;
+}
+
+/* Decode (and, if semantic != 0, validate) one module w[0..n).  Instruction
+ * j of the valid prefix goes to idx_off[j] / idx_op[j] when they are given.
+ * Returns 0, or -1 if memory for the semantic stage could not be had. */
+static int check_module(const uint32_t *w, uint64_t n, int semantic, uint32_t *idx_off, uint16_t *idx_op,
+                        orc_result *r) {
+  r->code = ORC_OK;
+  r->sem_mask = 0;
+  r->err_word = 0xFFFFFFFFu;
+  r->n_inst = 0;
+
+  /* 1. header, first failure wins */
+  if (n < 5) {
+    r->code = ORC_TRUNCATED_HEADER;
+    r->err_word = (uint32_t)n;
+    return 0;
+  }
+  if (w[0] != ORC_MAGIC) {
+    r->code = ORC_BAD_MAGIC;
+    r->err_word = 0;
+    return 0;
+  }
+  uint32_t major = (w[1] >> 16) & 0xFFu, minor = (w[1] >> 8) & 0xFFu;
+  if ((w[1] & 0xFF0000FFu) != 0 || major != 1 || minor > 6) {
+    r->code = ORC_BAD_VERSION;
+    r->err_word = 1;
+    return 0;
+  }
+  if (w[4] != 0) {
+    r->code = ORC_BAD_SCHEMA;
+    r->err_word = 4;
+    return 0;
+  }
+  uint32_t bound = w[3];
+
+  /* 2. walk the instruction chain from the first word after the header */
+  uint64_t p = 5, k = 0;
+  while (p < n) {
+    uint32_t wc = w[p] >> 16, op = w[p] & 0xFFFFu;
+    const orc_inst *g = lookup(op);
+    uint32_t code = ORC_OK;
+    if (wc == 0 || p + wc > n) code = ORC_BAD_WORD_COUNT;
+    else if (g == NULL) code = ORC_UNKNOWN_OPCODE;
+    else if ((g->word_count != 0 && wc != g->word_count) || (g->word_count == 0 && wc < 3))
+      code = ORC_BAD_WORD_COUNT;
+    else if (op == ORC_OPNAME && !string_ok(w + p + 2, wc - 2))
+      code = ORC_BAD_STRING;
+    if (code != ORC_OK) {
+      r->code = code;
+      r->err_word = (uint32_t)p;
+      r->n_inst = (uint32_t)k;
+      return 0;
+    }
+    if (idx_off) idx_off[k] = (uint32_t)p;
+    if (idx_op) idx_op[k] = (uint16_t)op;
+    ++k;
+    p += wc;
+  }
+  r->n_inst = (uint32_t)k;
+  if (!semantic) return 0;
+
+  /* 3. ID checks over every ID-role word */
+  uint64_t cap = n; /* an upper bound on the number of ID words */
+  uint32_t *defs = (uint32_t *)malloc((cap + 1) * sizeof(uint32_t));
+  uint32_t *uses = (uint32_t *)malloc((cap + 1) * sizeof(uint32_t));
+  if (!defs || !uses) {
+    free(defs);
+    free(uses);
+    return -1;
+  }
+  uint64_t nd = 0, nu = 0;
+  int oob = 0;
+  p = 5;
+  while (p < n) {
+    uint32_t wc = w[p] >> 16, op = w[p] & 0xFFFFu;
+    const orc_inst *g = lookup(op);
+    for (uint32_t s = 0; g->roles[s] != '\0' && g->roles[s] != 'S'; ++s) {
+      char role = g->roles[s];
+      if (role != 'U' && role != 'D') continue;
+      uint32_t v = w[p + 1 + s];
+      if (v == 0 || v >= bound) {
+        oob = 1;
+        continue;
+      }
+      if (role == 'D') defs[nd++] = v;
+      else uses[nu++] = v;
+    }
+    p += wc;
+  }
+  qsort(defs, nd, sizeof(uint32_t), cmp_u32);
+  int dup = 0, undef = 0;
+  for (uint64_t i = 1; i < nd; ++i)
+    if (defs[i] == defs[i - 1]) dup = 1;
+  for (uint64_t i = 0; i < nu; ++i)
+    if (!contains(defs, nd, uses[i])) undef = 1;
+  free(defs);
+  free(uses);
+  r->sem_mask = (oob ? 1u : 0u) | (dup ? 2u : 0u) | (undef ? 4u : 0u);
+  if (oob) r->code = ORC_ID_OUT_OF_BOUND;
+  else if (dup) r->code = ORC_DUPLICATE_ID;
+  else if (undef) r->code = ORC_UNDEFINED_ID;
+  return 0;
+}
+
+/* Batched entry points over CSR-packed modules: module m is
+ * words[mod_off[m] .. mod_off[m+1]).  Index arrays, when given, are gapped
+ * CSR: module m's instruction j is at idx_off[mod_off[m] + j] (a word offset
+ * within the module) and idx_op[mod_off[m] + j].  Returns 0 or -1. */
+int oracle_validate(const uint32_t *words, const int64_t *mod_off, int64_t n_modules, int semantic,
+                    uint32_t *idx_off, uint16_t *idx_op, orc_result *results) {
+  for (int64_t m = 0; m < n_modules; ++m) {
+    int64_t b = mod_off[m], e = mod_off[m + 1];
+    if (e < b) return -1;
+    if (check_module(words + b, (uint64_t)(e - b), semantic, idx_off ? idx_off + b : NULL,
+                     idx_op ? idx_op + b : NULL, &results[m]) != 0)
+      return -1;
+  }
+  return 0;
+}
+
+/* Records mode of the disassembler: for each instruction of the valid prefix
+ * of each module, its opcode, its non-string operand words and the bytes of
+ * its string (excluding the NUL).  Output arrays are sized by the caller for
+ * the whole batch (n_words entries each is always enough); rec_mod_off gets
+ * the record CSR (n_modules+1).  Returns 0, or -1 on bad offsets. */
+int oracle_records(const uint32_t *words, const int64_t *mod_off, int64_t n_modules, uint16_t *op_out,
+                   int32_t *opnd_off, uint32_t *opnd, int32_t *str_off, uint8_t *chars, int64_t *rec_mod_off) {
+  int64_t nr = 0, no = 0, nc = 0;
+  opnd_off[0] = 0;
+  str_off[0] = 0;
+  rec_mod_off[0] = 0;
+  for (int64_t m = 0; m < n_modules; ++m) {
+    int64_t b = mod_off[m], e = mod_off[m + 1];
+    if (e < b) return -1;
+    const uint32_t *w = words + b;
+    uint64_t n = (uint64_t)(e - b);
+    orc_result r;
+    check_module(w, n, 0, NULL, NULL, &r);
+    if (r.code == ORC_OK || r.code >= ORC_BAD_WORD_COUNT) {
+      uint64_t p = 5;
+      for (uint32_t j = 0; j < r.n_inst; ++j) {
+        uint32_t wc = w[p] >> 16, op = w[p] & 0xFFFFu;
+        op_out[nr] = (uint16_t)op;
+        if (op == ORC_OPNAME) {
+          opnd[no++] = w[p + 1];
+          const uint8_t *bytes = (const uint8_t *)(w + p + 2);
+          for (uint64_t i = 0; bytes[i] != 0; ++i) chars[nc++] = bytes[i];
+        } else {
+          for (uint32_t s = 1; s < wc; ++s) opnd[no++] = w[p + s];
+        }
+        ++nr;
+        opnd_off[nr] = (int32_t)no;
+        str_off[nr] = (int32_t)nc;
+        p += wc;
+      }
+    }
+    rec_mod_off[m + 1] = nr;
+  }
+  return 0;
+}
+
+/* Upper bound on encoder output: every module valid. */
+int64_t oracle_encode_bound(int64_t n_modules, int64_t n_records, int64_t n_opnd, int64_t n_chars) {
+  return 5 * n_modules + n_records + n_opnd + n_records + n_chars / 4;
+}
+
+/* Encode every module's records to SPIR-V words (the library's write step,
+ * bound recomputed as 1 + the largest ID operand, or 1 when there is none).
+ * A module with a failing record produces no words at all; enc_code[m] and
+ * enc_bad_record[m] (module-relative record index, -1 if none) say why.
+ * word_mod_off (n_modules+1) is the dense CSR of the output.  Returns the
+ * number of words written, or -1 if words_cap is too small. */
+int64_t oracle_encode(const uint16_t *op, const int32_t *opnd_off, const uint32_t *opnd, const int32_t *str_off,
+                      const uint8_t *chars, const int64_t *rec_mod_off, int64_t n_modules, uint32_t version_word,
+                      uint32_t generator_word, uint32_t *words_out, int64_t *word_mod_off, int64_t words_cap,
+                      uint32_t *enc_code, int64_t *enc_bad_record) {
+  int64_t out = 0;
+  word_mod_off[0] = 0;
+  for (int64_t m = 0; m < n_modules; ++m) {
+    int64_t r0 = rec_mod_off[m], r1 = rec_mod_off[m + 1];
+    uint32_t code = ORC_ENC_OK;
+    int64_t bad = -1;
+    uint64_t max_id = 0;
+    int any_id = 0;
+    uint64_t total = 5;
+    /* checks first: a failing module writes nothing */
+    for (int64_t j = r0; j < r1 && code == ORC_ENC_OK; ++j) {
+      const orc_inst *g = lookup(op[j]);
+      int64_t n_ops = opnd_off[j + 1] - opnd_off[j];
+      int64_t n_chars = str_off[j + 1] - str_off[j];
+      uint64_t wc = 0;
+      if (g == NULL) code = ORC_ENC_UNKNOWN_OPCODE;
+      else if ((g->word_count == 0 && n_ops != 1) || (g->word_count != 0 && n_ops != g->word_count - 1))
+        code = ORC_ENC_OPERAND_COUNT;
+      else if (g->word_count != 0 && n_chars != 0) code = ORC_ENC_BAD_STRING;
+      else if (g->word_count == 0 && memchr(chars + str_off[j], 0, (size_t)n_chars) != NULL)
+        code = ORC_ENC_BAD_STRING;
+      else {
+        wc = 1 + (uint64_t)n_ops + (g->word_count == 0 ? (uint64_t)n_chars / 4 + 1 : 0);
+        if (wc > 65535) code = ORC_ENC_TOO_LONG;
+      }
+      if (code == ORC_ENC_OK) {
+        for (int64_t s = 0; s < n_ops; ++s) {
+          char role = g->roles[s];
+          if (role != 'U' && role != 'D') continue;
+          uint32_t v = opnd[opnd_off[j] + s];
+          if (v == 0xFFFFFFFFu) {
+            code = ORC_ENC_BAD_ID;
+            break;
+          }
+          if (!any_id || v > max_id) max_id = v;
+          any_id = 1;
+        }
+      }
+      if (code != ORC_ENC_OK) bad = j - r0;
+      total += wc;
+    }
+    enc_code[m] = code;
+    enc_bad_record[m] = bad;
+    if (code != ORC_ENC_OK) {
+      word_mod_off[m + 1] = out;
+      continue;
+    }
+    if (out + (int64_t)total > words_cap) return -1;
+    uint32_t *w = words_out + out;
+    w[0] = ORC_MAGIC;
+    w[1] = version_word;
+    w[2] = generator_word;
+    w[3] = any_id ? (uint32_t)(max_id + 1) : 1u;
+    w[4] = 0;
+    uint64_t p = 5;
+    for (int64_t j = r0; j < r1; ++j) {
+      const orc_inst *g = lookup(op[j]);
+      int64_t n_ops = opnd_off[j + 1] - opnd_off[j];
+      int64_t n_chars = str_off[j + 1] - str_off[j];
+      uint64_t str_words = g->word_count == 0 ? (uint64_t)n_chars / 4 + 1 : 0;
+      uint64_t wc = 1 + (uint64_t)n_ops + str_words;
+      w[p] = (uint32_t)((wc << 16) | op[j]);
+      for (int64_t s = 0; s < n_ops; ++s) w[p + 1 + s] = opnd[opnd_off[j] + s];
+      for (uint64_t s = 0; s < str_words; ++s) {
+        uint32_t word = 0;
+        for (uint64_t b = 0; b < 4; ++b) {
+          int64_t ci = 4 * (int64_t)s + (int64_t)b;
+          uint32_t byte = ci < n_chars ? chars[str_off[j] + ci] : 0u;
+          word |= byte << (8 * b);
+        }
+        w[p + 1 + n_ops + s] = word;
+      }
+      p += wc;
+    }
+    out += (int64_t)total;
+    word_mod_off[m + 1] = out;
+  }
+  return out;
+}

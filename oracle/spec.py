@@ -1,0 +1,134 @@
+"""Independent definitional checker for tiny modules (test infrastructure).
+
+A second, deliberately different statement of the validator contract used by
+the brute-force tests to cross-check ``oracle.c``: it reads the module as a
+little-endian byte string, describes each instruction by its operand kinds and
+uses Python sets for the ID rules.  Sources: SPIR-V module layout as the
+toolkit writes it (section "SPIR-V Library": header listing, bound recomputed
+at write; section "Parsing Operand Kinds": operand words and word counts), the
+SSA single-assignment rule (section "Enabling Function Composition") and the
+validation stage (section "Validation Rules").  Slow; only for small inputs.
+"""
+from __future__ import annotations
+
+import struct
+from collections import Counter
+
+# opcode -> (operand kinds after the first word); "str" marks a literal string
+# running to the end of the instruction.  Fixed-size instructions have exactly
+# len(kinds) operand words.
+KINDS = {
+    5: ("id", "str"),                       # OpName target, name
+    14: ("lit", "lit"),                     # OpMemoryModel addressing, memory
+    17: ("lit",),                           # OpCapability
+    21: ("result", "lit", "lit"),           # OpTypeInt result, width, signedness
+    43: ("id", "result", "lit"),            # OpConstant type, result, value
+    54: ("id", "result", "lit", "id"),      # OpFunction type, result, control, fn type
+    56: (),                                 # OpFunctionEnd
+    61: ("id", "result", "id"),             # OpLoad type, result, pointer
+    62: ("id", "id"),                       # OpStore pointer, object
+    128: ("id", "result", "id", "id"),      # OpIAdd type, result, a, b
+    248: ("result",),                       # OpLabel
+    253: (),                                # OpReturn
+}
+
+
+def _string_words_ok(raw: bytes) -> bool:
+    # the literal ends at its first NUL; the NUL must sit in the final word and
+    # the rest of that word must be NUL padding
+    nul = raw.find(b"\x00")
+    if nul < 0:
+        return False
+    return nul >= len(raw) - 4 and raw[nul:] == b"\x00" * (len(raw) - nul)
+
+
+def check(words, semantic: bool = True):
+    """(code, sem_mask, err_word, n_inst, [(offset, opcode), ...])."""
+    w = [int(x) & 0xFFFFFFFF for x in words]
+    n = len(w)
+    raw = struct.pack("<%dI" % n, *w)
+    if n < 5:
+        return (1, 0, n, 0, [])
+    if raw[0:4] != bytes([0x03, 0x02, 0x23, 0x07]):
+        return (2, 0, 0, 0, [])
+    ver = raw[4:8]  # bytes: reserved, minor, major, reserved
+    if ver[0] != 0 or ver[3] != 0 or ver[2] != 1 or ver[1] > 6:
+        return (3, 0, 1, 0, [])
+    if w[4] != 0:
+        return (4, 0, 4, 0, [])
+    bound = w[3]
+    insts = []
+    pos = 5
+    while pos < n:
+        count, opcode = divmod(w[pos], 1 << 16)
+        end = pos + count
+        if count == 0 or end > n:
+            return (5, 0, pos, len(insts), insts)
+        if opcode not in KINDS:
+            return (6, 0, pos, len(insts), insts)
+        kinds = KINDS[opcode]
+        if "str" in kinds:
+            if count < 2 + 1:
+                return (5, 0, pos, len(insts), insts)
+            if not _string_words_ok(raw[4 * (pos + 2):4 * end]):
+                return (7, 0, pos, len(insts), insts)
+        elif count != 1 + len(kinds):
+            return (5, 0, pos, len(insts), insts)
+        insts.append((pos, opcode))
+        pos = end
+    if not semantic:
+        return (0, 0, 0xFFFFFFFF, len(insts), insts)
+    defined = Counter()
+    used = set()
+    out_of_bound = False
+    for pos, opcode in insts:
+        for slot, kind in enumerate(KINDS[opcode]):
+            if kind not in ("id", "result"):
+                continue
+            v = w[pos + 1 + slot]
+            if not (0 < v < bound):
+                out_of_bound = True
+            elif kind == "result":
+                defined[v] += 1
+            else:
+                used.add(v)
+    dup = any(c > 1 for c in defined.values())
+    undef = bool(used - set(defined))
+    mask = (1 if out_of_bound else 0) | (2 if dup else 0) | (4 if undef else 0)
+    code = 8 if out_of_bound else 9 if dup else 10 if undef else 0
+    return (code, mask, 0xFFFFFFFF, len(insts), insts)
+
+
+def encode_module(records, version_word=0x00010600, generator_word=0):
+    """Words of one module from records [(opcode, [operands], name_bytes)],
+    or (code, bad_index) when a record cannot be encoded."""
+    body = []
+    ids = []
+    for j, (opcode, operands, name) in enumerate(records):
+        if opcode not in KINDS:
+            return (1, j)
+        kinds = KINDS[opcode]
+        is_name = "str" in kinds
+        want = 1 if is_name else len(kinds)
+        if len(operands) != want:
+            return (2, j)
+        if (not is_name and len(name) > 0) or (is_name and b"\x00" in name):
+            return (3, j)
+        sw = b""
+        if is_name:
+            padded = name + b"\x00"
+            padded += b"\x00" * (-len(padded) % 4)
+            sw = padded
+        count = 1 + len(operands) + len(sw) // 4
+        if count >= 1 << 16:
+            return (4, j)
+        for kind, v in zip(kinds, operands):
+            if kind in ("id", "result"):
+                if v == 0xFFFFFFFF:
+                    return (5, j)
+                ids.append(v)
+        body.append(count << 16 | opcode)
+        body.extend(operands)
+        body.extend(struct.unpack("<%dI" % (len(sw) // 4), sw))
+    bound = max(ids) + 1 if ids else 1
+    return [0x07230203, version_word, generator_word, bound, 0] + body
