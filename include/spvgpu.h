@@ -1,0 +1,178 @@
+/*
+ * spvgpu -- batched SPIR-V decode, validate and encode on AMD Instinct
+ * MI355X (gfx950).  C ABI.
+ *
+ * What the library computes comes from the Beehive SPIR-V Toolkit paper
+ * (arXiv 2305.09493): SPIR-V modules are streams of 32-bit words that begin
+ * with a 5-word header (magic, version, generator, bound, schema; section
+ * "SPIR-V Library", header listing) followed by instructions whose first word
+ * holds the word count (high 16 bits) and opcode (low 16 bits); every
+ * instruction and operand writes its own words and reports its word count
+ * (section "Parsing Operand Kinds"); IDs are allocated once per module and
+ * each is assigned once (section "Enabling Function Composition"); the bound
+ * is recomputed when the module is written; the disassembler turns binaries
+ * back into instructions (section "Dis/Assembler") and the library validates
+ * modules before storing them (section "Validation Rules").
+ *
+ * Batches are CSR-packed: module m is words[mod_off[m] .. mod_off[m+1]).
+ * All pointers to batch data, outputs and the workspace are DEVICE pointers
+ * (hipMalloc'd or torch CUDA tensors) owned by the caller; the library owns
+ * only the context.  Every call is asynchronous on the given stream
+ * (hipStream_t passed as void*; NULL = the default stream), performs no host
+ * synchronisation and no allocation, and may be captured into a HIP graph.
+ * Calls that share a workspace must be ordered (same stream or events).
+ *
+ * Return values are synchronous and report argument / environment problems
+ * only (SPV_ERR_*).  Problems in the data never fail a call: they are
+ * reported per module in spv_result / the encode status arrays.
+ */
+#ifndef SPVGPU_H
+#define SPVGPU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- call status ------------------------------------------------------- */
+#define SPV_SUCCESS 0
+#define SPV_ERR_INVALID_ARG (-1) /* null pointer, negative size, misaligned words, bad flags */
+#define SPV_ERR_CAPACITY (-2)    /* idx_cap < n_words, or words_cap < spv_encode_bound */
+#define SPV_ERR_WORKSPACE (-3)   /* ws too small (see spv_workspace_size) or null */
+#define SPV_ERR_HIP (-4)         /* a HIP runtime call failed; see spv_last_hip_error */
+#define SPV_ERR_LIMIT (-5)       /* a module has >= 2^32 words, or too many modules */
+
+/* ---- per-module result codes (decode / validate) ------------------------
+ * Checks run in stages; the first failing stage decides the code.
+ *   header : n < 5 -> TRUNCATED_HEADER (err_word = n); magic != 0x07230203
+ *            -> BAD_MAGIC (0); version word with non-zero reserved bytes,
+ *            major != 1 or minor > 6 -> BAD_VERSION (1); schema != 0 ->
+ *            BAD_SCHEMA (4).
+ *   parse  : walk from word 5; at each instruction start p, in this order:
+ *            word count 0 or past the module end -> BAD_WORD_COUNT; opcode
+ *            not in the grammar table -> UNKNOWN_OPCODE; word count not the
+ *            table's -> BAD_WORD_COUNT; OpName string not NUL-terminated in
+ *            its last word with zero padding -> BAD_STRING.  err_word = p
+ *            (word offset in the module), n_inst = instructions before p.
+ *   semantic (validate only): over ID-role words, id == 0 or id >= bound ->
+ *            OOB (mask 1); a result ID defined twice -> DUP (mask 2); an ID
+ *            used but defined nowhere in the module -> UNDEF (mask 4).
+ *            code = first of OOB > DUP > UNDEF; err_word = 0xFFFFFFFF.
+ * For SPV_OK and semantic codes err_word is 0xFFFFFFFF.                    */
+#define SPV_OK 0
+#define SPV_E_TRUNCATED_HEADER 1
+#define SPV_E_BAD_MAGIC 2
+#define SPV_E_BAD_VERSION 3
+#define SPV_E_BAD_SCHEMA 4
+#define SPV_E_BAD_WORD_COUNT 5
+#define SPV_E_UNKNOWN_OPCODE 6
+#define SPV_E_BAD_STRING 7
+#define SPV_E_ID_OUT_OF_BOUND 8
+#define SPV_E_DUPLICATE_ID 9
+#define SPV_E_UNDEFINED_ID 10
+
+/* ---- encode status codes (per module) ---------------------------------- */
+#define SPV_ENC_OK 0
+#define SPV_ENC_UNKNOWN_OPCODE 1 /* opcode not in the grammar table */
+#define SPV_ENC_OPERAND_COUNT 2  /* non-string operand count differs from the table (OpName: 1) */
+#define SPV_ENC_BAD_STRING 3     /* string on a non-OpName record, or NUL inside an OpName string */
+#define SPV_ENC_TOO_LONG 4       /* word count would exceed 65535 */
+#define SPV_ENC_BAD_ID 5         /* an ID operand equals 0xFFFFFFFF (bound not representable) */
+
+/* Grammar table (the twelve opcodes of the synthetic workloads): opcode,
+ * word count, operand roles (U = ID use, D = result ID, L = literal,
+ * S = string words):
+ *   OpName 5 (>=3, U S...), OpMemoryModel 14 (3, L L), OpCapability 17
+ *   (2, L), OpTypeInt 21 (4, D L L), OpConstant 43 (4, U D L), OpFunction
+ *   54 (5, U D L U), OpFunctionEnd 56 (1), OpLoad 61 (4, U D U), OpStore 62
+ *   (3, U U), OpIAdd 128 (5, U D U U), OpLabel 248 (2, D), OpReturn 253 (1). */
+
+typedef struct spv_ctx spv_ctx;
+
+/* 16 bytes per module. */
+typedef struct {
+  uint32_t code;     /* SPV_OK or SPV_E_* */
+  uint32_t sem_mask; /* 1 OOB | 2 DUP | 4 UNDEF (validate; 0 otherwise) */
+  uint32_t err_word; /* offending word offset within the module, or 0xFFFFFFFF */
+  uint32_t n_inst;   /* instructions decoded (before the failing one, if any) */
+} spv_result;
+
+/* Create a context on HIP device `hip_device` (holds device properties and
+ * launch tuning).  *out receives the handle.  SPV_ERR_HIP if the device
+ * cannot be used. */
+int spv_create(spv_ctx **out, int hip_device);
+int spv_destroy(spv_ctx *ctx);
+
+/* Device-side error text of the last failing HIP call on this context. */
+const char *spv_last_hip_error(spv_ctx *ctx);
+
+/* Launch tuning (0 = keep the built-in default).  blocks_per_cu sets the
+ * persistent grid of the decode/validate kernel; encode_block sets the
+ * records per encode block (a multiple of 256). */
+int spv_set_tuning(spv_ctx *ctx, int blocks_per_cu, int encode_block);
+
+/* Bytes of workspace that spv_decode / spv_validate need for a batch of
+ * n_modules modules and n_words words (about 8 bytes per word plus small
+ * per-module and per-tile state).  The workspace needs no initialisation
+ * and may be reused by later calls on the same stream. */
+int spv_workspace_size(spv_ctx *ctx, int64_t n_modules, int64_t n_words, size_t *bytes);
+
+/* Decode: header and parse stages; results[m] for every module, and, when
+ * idx_off / idx_op are non-NULL, the instruction index in gapped CSR form:
+ * module m's instruction j is idx_off[mod_off[m] + j] (word offset of its
+ * first word within the module) and idx_op[mod_off[m] + j] (opcode), for
+ * j < results[m].n_inst.  Entries past n_inst are unspecified.  idx_cap must
+ * be >= n_words when the index is requested.
+ *   words   : uint32[n_words], 16-byte aligned
+ *   mod_off : int64[n_modules+1], mod_off[0] = 0, non-decreasing,
+ *             mod_off[n_modules] = n_words; each module < 2^32 words
+ *   results : spv_result[n_modules]
+ *   ws      : workspace of ws_bytes >= spv_workspace_size(...)          */
+int spv_decode(spv_ctx *ctx, const uint32_t *words, const int64_t *mod_off, int64_t n_modules, int64_t n_words,
+               uint32_t *idx_off, uint16_t *idx_op, int64_t idx_cap, spv_result *results, void *ws,
+               size_t ws_bytes, void *stream);
+
+/* Validate: decode plus the semantic stage (bound, define-once, undefined
+ * IDs).  Same arguments as spv_decode, plus option_flags (must be 0; reserved
+ * for the paper's module-level rules). */
+int spv_validate(spv_ctx *ctx, const uint32_t *words, const int64_t *mod_off, int64_t n_modules, int64_t n_words,
+                 uint32_t *idx_off, uint16_t *idx_op, int64_t idx_cap, spv_result *results, uint32_t option_flags,
+                 void *ws, size_t ws_bytes, void *stream);
+
+/* Host-side upper bound on the words spv_encode may write:
+ * 5*n_modules + n_records + n_opnd_words + n_string_records + n_chars/4. */
+int spv_encode_bound(int64_t n_modules, int64_t n_records, int64_t n_opnd_words, int64_t n_string_records,
+                     int64_t n_chars, int64_t *max_words);
+
+/* Bytes of workspace spv_encode needs. */
+int spv_encode_workspace_size(spv_ctx *ctx, int64_t n_modules, int64_t n_records, size_t *bytes);
+
+/* Encode records to SPIR-V words (the library's write step, section "SPIR-V
+ * Library": each record writes (wc << 16) | opcode, its operands and its
+ * string packed little-endian and zero padded; the header gets magic,
+ * version_word, generator_word, bound = 1 + the largest ID operand (1 if
+ * none), schema 0).  Records are CSR by module: module m owns records
+ * rec_mod_off[m] .. rec_mod_off[m+1]; record r has opcode op[r], operands
+ * opnd[opnd_off[r] .. opnd_off[r+1]) and string bytes
+ * chars[str_off[r] .. str_off[r+1]) (no NUL; only OpName may have one).
+ * A module with a failing record writes no words; enc_code[m] /
+ * enc_bad_record[m] (module-relative index of its first failing record, -1
+ * if none) say why.  word_mod_off (n_modules+1) receives the dense output
+ * CSR.  words_cap must be >= spv_encode_bound(...).
+ * Device pointers: op uint16[n_records], opnd_off int32[n_records+1],
+ * opnd uint32[opnd_off[n]], str_off int32[n_records+1], chars uint8,
+ * rec_mod_off int64[n_modules+1], words_out uint32[words_cap],
+ * word_mod_off int64[n_modules+1], enc_code uint32[n_modules],
+ * enc_bad_record int64[n_modules]. */
+int spv_encode(spv_ctx *ctx, const uint16_t *op, const int32_t *opnd_off, const uint32_t *opnd, const int32_t *str_off,
+               const uint8_t *chars, const int64_t *rec_mod_off, int64_t n_modules, int64_t n_records,
+               uint32_t version_word, uint32_t generator_word, uint32_t *words_out, int64_t *word_mod_off,
+               int64_t words_cap, uint32_t *enc_code, int64_t *enc_bad_record, void *ws, size_t ws_bytes,
+               void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPVGPU_H */

@@ -1,0 +1,220 @@
+"""spvgpu: batched SPIR-V decode / validate / encode on MI355X (gfx950).
+
+A thin ctypes binding of ``libspvgpu.so`` (C ABI declared in
+``include/spvgpu.h``).  torch is used only for device memory and streams:
+every step of decode, validate and encode runs in the library's HIP kernels.
+The binding fails loudly when the library is missing; there is no CPU path.
+
+The functions take CUDA (ROCm) tensors:
+  words   : int32 or uint32 [W] (bit pattern of the SPIR-V words)
+  mod_off : int64 [M+1]
+and return CUDA tensors on the current stream (no host synchronisation).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+from typing import Optional
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libspvgpu.so")
+
+SPV_SUCCESS = 0
+ERRORS = {-1: "invalid argument", -2: "capacity", -3: "workspace", -4: "HIP error", -5: "limit"}
+
+OK, E_TRUNCATED_HEADER, E_BAD_MAGIC, E_BAD_VERSION, E_BAD_SCHEMA = 0, 1, 2, 3, 4
+E_BAD_WORD_COUNT, E_UNKNOWN_OPCODE, E_BAD_STRING = 5, 6, 7
+E_ID_OUT_OF_BOUND, E_DUPLICATE_ID, E_UNDEFINED_ID = 8, 9, 10
+
+_lib = None
+_lock = threading.Lock()
+
+
+class SpvError(RuntimeError):
+    pass
+
+
+def load_library():
+    """Load libspvgpu.so (built by ``paper_2305_09493_amd.build``)."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise SpvError(f"{LIB_PATH} is missing: build it with `python -m paper_2305_09493_amd.build` "
+                           "(the library has no CPU fallback)")
+        lib = ctypes.CDLL(LIB_PATH)
+        P, I64, U32, SZ = ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint32, ctypes.c_size_t
+        lib.spv_create.argtypes = [ctypes.POINTER(P), ctypes.c_int]
+        lib.spv_destroy.argtypes = [P]
+        lib.spv_last_hip_error.argtypes = [P]
+        lib.spv_last_hip_error.restype = ctypes.c_char_p
+        lib.spv_set_tuning.argtypes = [P, ctypes.c_int, ctypes.c_int]
+        lib.spv_workspace_size.argtypes = [P, I64, I64, ctypes.POINTER(SZ)]
+        lib.spv_decode.argtypes = [P, P, P, I64, I64, P, P, I64, P, P, SZ, P]
+        lib.spv_validate.argtypes = [P, P, P, I64, I64, P, P, I64, P, U32, P, SZ, P]
+        lib.spv_encode_bound.argtypes = [I64, I64, I64, I64, I64, ctypes.POINTER(I64)]
+        lib.spv_encode_workspace_size.argtypes = [P, I64, I64, ctypes.POINTER(SZ)]
+        lib.spv_encode.argtypes = [P, P, P, P, P, P, P, I64, I64, U32, U32, P, P, I64, P, P, P, SZ, P]
+        for name in ("spv_create", "spv_destroy", "spv_set_tuning", "spv_workspace_size", "spv_decode",
+                     "spv_validate", "spv_encode_bound", "spv_encode_workspace_size", "spv_encode"):
+            getattr(lib, name).restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+EXPORTS = ("spv_create", "spv_destroy", "spv_last_hip_error", "spv_set_tuning", "spv_workspace_size",
+           "spv_decode", "spv_validate", "spv_encode_bound", "spv_encode_workspace_size", "spv_encode")
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+class Context:
+    """One spv_ctx on a device plus a reusable workspace tensor."""
+
+    def __init__(self, device: int = 0):
+        self.lib = load_library()
+        self.device = device
+        h = ctypes.c_void_p()
+        rc = self.lib.spv_create(ctypes.byref(h), device)
+        if rc != SPV_SUCCESS:
+            raise SpvError(f"spv_create failed ({ERRORS.get(rc, rc)})")
+        self.h = h
+        self._ws = None
+
+    def close(self):
+        if self.h is not None:
+            self.lib.spv_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def check(self, rc: int, what: str):
+        if rc != SPV_SUCCESS:
+            detail = self.lib.spv_last_hip_error(self.h).decode() if rc == -4 else ""
+            raise SpvError(f"{what} failed: {ERRORS.get(rc, rc)} {detail}")
+
+    def set_tuning(self, blocks_per_cu: int = 0, encode_block: int = 0):
+        self.check(self.lib.spv_set_tuning(self.h, blocks_per_cu, encode_block), "spv_set_tuning")
+
+    def workspace(self, nbytes: int):
+        torch = _torch()
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=f"cuda:{self.device}")
+        return self._ws
+
+    def workspace_size(self, n_modules: int, n_words: int) -> int:
+        sz = ctypes.c_size_t()
+        self.check(self.lib.spv_workspace_size(self.h, n_modules, n_words, ctypes.byref(sz)), "spv_workspace_size")
+        return sz.value
+
+    def encode_workspace_size(self, n_modules: int, n_records: int) -> int:
+        sz = ctypes.c_size_t()
+        self.check(self.lib.spv_encode_workspace_size(self.h, n_modules, n_records, ctypes.byref(sz)),
+                   "spv_encode_workspace_size")
+        return sz.value
+
+
+_default = {}
+
+
+def context(device: Optional[int] = None) -> Context:
+    torch = _torch()
+    if device is None:
+        device = torch.cuda.current_device()
+    if device not in _default:
+        _default[device] = Context(device)
+    return _default[device]
+
+
+def _stream(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _run(semantic: bool, words, mod_off, index: bool, ctx: Optional[Context], stream, out=None, workspace=None):
+    torch = _torch()
+    ctx = ctx or context(words.device.index)
+    W = int(words.numel())
+    M = int(mod_off.numel()) - 1
+    assert words.is_cuda and mod_off.is_cuda and mod_off.dtype == torch.int64
+    assert words.dtype in (torch.int32, torch.uint32) and words.is_contiguous()
+    dev = words.device
+    if out is None:
+        results = torch.empty((M, 4), dtype=torch.int32, device=dev)
+        idx_off = torch.empty(W if index else 0, dtype=torch.int32, device=dev) if index else None
+        idx_op = torch.empty(W if index else 0, dtype=torch.int16, device=dev) if index else None
+    else:
+        results, idx_off, idx_op = out
+    ws_bytes = ctx.workspace_size(M, W)
+    ws = workspace if workspace is not None else ctx.workspace(ws_bytes)
+    args = [ctx.h, _ptr(words), _ptr(mod_off), M, W, _ptr(idx_off), _ptr(idx_op), W if index else 0,
+            _ptr(results)]
+    if semantic:
+        rc = ctx.lib.spv_validate(*args, 0, _ptr(ws), ws.numel(), _stream(stream))
+        ctx.check(rc, "spv_validate")
+    else:
+        rc = ctx.lib.spv_decode(*args, _ptr(ws), ws.numel(), _stream(stream))
+        ctx.check(rc, "spv_decode")
+    return results, idx_off, idx_op
+
+
+def validate(words, mod_off, index: bool = True, ctx: Optional[Context] = None, stream=None, out=None,
+             workspace=None):
+    """Per-module results int32[M, 4] (code, sem_mask, err_word, n_inst) and,
+    if index, the gapped-CSR instruction index (idx_off int32[W], idx_op
+    int16[W])."""
+    return _run(True, words, mod_off, index, ctx, stream, out, workspace)
+
+
+def decode(words, mod_off, index: bool = True, ctx: Optional[Context] = None, stream=None, out=None,
+           workspace=None):
+    return _run(False, words, mod_off, index, ctx, stream, out, workspace)
+
+
+def encode_bound(n_modules: int, n_records: int, n_opnd: int, n_string_records: int, n_chars: int) -> int:
+    lib = load_library()
+    out = ctypes.c_int64()
+    rc = lib.spv_encode_bound(n_modules, n_records, n_opnd, n_string_records, n_chars, ctypes.byref(out))
+    if rc != SPV_SUCCESS:
+        raise SpvError(f"spv_encode_bound failed: {ERRORS.get(rc, rc)}")
+    return out.value
+
+
+def encode(op, opnd_off, opnd, str_off, chars, rec_mod_off, version_word: int = 0x00010600,
+           generator_word: int = 0, words_cap: Optional[int] = None, ctx: Optional[Context] = None, stream=None):
+    """Encode CSR records (CUDA tensors: op int16/uint16 [N], opnd_off int32
+    [N+1], opnd int32 [*], str_off int32 [N+1], chars uint8 [*], rec_mod_off
+    int64 [M+1]).  Returns (words int32[cap], word_mod_off int64[M+1],
+    enc_code int32[M], enc_bad_record int64[M])."""
+    torch = _torch()
+    ctx = ctx or context(op.device.index)
+    dev = op.device
+    M = int(rec_mod_off.numel()) - 1
+    N = int(op.numel())
+    if words_cap is None:
+        words_cap = encode_bound(M, N, int(opnd.numel()), N, int(chars.numel()))
+    words = torch.empty(max(words_cap, 1), dtype=torch.int32, device=dev)
+    word_mod_off = torch.empty(M + 1, dtype=torch.int64, device=dev)
+    code = torch.empty(M, dtype=torch.int32, device=dev)
+    bad = torch.empty(M, dtype=torch.int64, device=dev)
+    ws_bytes = ctx.encode_workspace_size(M, N)
+    ws = ctx.workspace(ws_bytes)
+    rc = ctx.lib.spv_encode(ctx.h, _ptr(op), _ptr(opnd_off), _ptr(opnd), _ptr(str_off), _ptr(chars),
+                            _ptr(rec_mod_off), M, N, version_word, generator_word, _ptr(words), _ptr(word_mod_off),
+                            words_cap, _ptr(code), _ptr(bad), _ptr(ws), ws.numel(), _stream(stream))
+    ctx.check(rc, "spv_encode")
+    return words, word_mod_off, code, bad

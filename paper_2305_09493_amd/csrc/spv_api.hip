@@ -1,0 +1,240 @@
+// C ABI of spvgpu: argument checks, workspace layout and launch order.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "spv_internal.h"
+
+struct spv_ctx {
+  int device;
+  int n_cu;
+  int blocks_per_cu;   // persistent grid of the decode/validate kernels
+  int encode_block;    // records per encode block
+  hipError_t last;
+  char msg[256];
+};
+
+namespace spv {
+int main_occupancy();
+}
+
+namespace {
+
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = true;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) {
+      ok = false;
+      return;
+    }
+    if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+int fail_hip(spv_ctx* ctx, hipError_t e) {
+  if (ctx) {
+    ctx->last = e;
+    snprintf(ctx->msg, sizeof(ctx->msg), "%s", hipGetErrorString(e));
+  }
+  return SPV_ERR_HIP;
+}
+
+int check_launch(spv_ctx* ctx) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail_hip(ctx, e);
+  return SPV_SUCCESS;
+}
+
+int run_validate(spv_ctx* ctx, const uint32_t* words, const int64_t* mod_off, int64_t n_modules, int64_t n_words,
+                 uint32_t* idx_off, uint16_t* idx_op, int64_t idx_cap, spv_result* results, int semantic, void* ws,
+                 size_t ws_bytes, void* stream) {
+  if (!ctx) return SPV_ERR_INVALID_ARG;
+  if (n_modules < 0 || n_words < 0) return SPV_ERR_INVALID_ARG;
+  if (n_modules >= (int64_t(1) << 31) - 1) return SPV_ERR_LIMIT;
+  if (n_modules == 0) return n_words == 0 ? SPV_SUCCESS : SPV_ERR_INVALID_ARG;
+  if (!mod_off || !results) return SPV_ERR_INVALID_ARG;
+  if (n_words > 0 && (!words || (reinterpret_cast<uintptr_t>(words) & 15u))) return SPV_ERR_INVALID_ARG;
+  bool index = idx_off != nullptr || idx_op != nullptr;
+  if (index && (!idx_off || !idx_op)) return SPV_ERR_INVALID_ARG;
+  if (index && idx_cap < n_words) return SPV_ERR_CAPACITY;
+  spv::Layout L = spv::make_layout(n_modules, n_words);
+  if (!ws || ws_bytes < L.total) return SPV_ERR_WORKSPACE;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail_hip(ctx, hipErrorInvalidDevice);
+  char* base = static_cast<char*>(ws);
+  spv::VParams p;
+  p.words = words;
+  p.mod_off = mod_off;
+  p.M = n_modules;
+  p.W = n_words;
+  p.n_tiles = (n_words + spv::kTileWords - 1) / spv::kTileWords;
+  p.idx_off = idx_off;
+  p.idx_op = idx_op;
+  p.results = results;
+  p.ctrl = reinterpret_cast<uint32_t*>(base + L.ctrl);
+  p.tileA = reinterpret_cast<unsigned long long*>(base + L.tileA);
+  p.tileB = reinterpret_cast<unsigned long long*>(base + L.tileB);
+  p.tfm = reinterpret_cast<int32_t*>(base + L.tfm);
+  p.mods = reinterpret_cast<spv::ModState*>(base + L.mods);
+  p.idmap = reinterpret_cast<unsigned long long*>(base + L.idmap);
+  p.semantic = semantic;
+  p.index = index ? 1 : 0;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+
+  int64_t plan_units = n_modules > p.n_tiles ? n_modules : p.n_tiles;
+  int64_t pg = plan_units / 256 + 1;
+  int64_t chunks = n_words / 16384 + 1;
+  if (semantic && chunks > pg) pg = chunks;
+  int plan_grid = int(pg > 4096 ? 4096 : pg);
+  spv::launch_plan(p, plan_grid, s);
+  int r = check_launch(ctx);
+  if (r) return r;
+  int64_t grid = int64_t(ctx->n_cu) * ctx->blocks_per_cu;
+  if (grid > p.n_tiles) grid = p.n_tiles;
+  if (grid > 0) {
+    spv::launch_main(p, int(grid), s);
+    if ((r = check_launch(ctx))) return r;
+  }
+  if (semantic) {
+    spv::launch_finalize(p, 1, s);
+    if ((r = check_launch(ctx))) return r;
+    int64_t g2 = int64_t(ctx->n_cu) * 2;
+    if (g2 > p.n_tiles) g2 = p.n_tiles;
+    if (g2 > 0) {
+      spv::launch_pass2(p, int(g2), s);
+      if ((r = check_launch(ctx))) return r;
+    }
+  }
+  spv::launch_finalize(p, 2, s);
+  return check_launch(ctx);
+}
+
+}  // namespace
+
+extern "C" {
+
+int spv_create(spv_ctx** out, int hip_device) {
+  if (!out) return SPV_ERR_INVALID_ARG;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || hip_device < 0 || hip_device >= n) return SPV_ERR_HIP;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, hip_device) != hipSuccess) return SPV_ERR_HIP;
+  spv_ctx* c = new spv_ctx;
+  c->device = hip_device;
+  c->n_cu = prop.multiProcessorCount;
+  {
+    DeviceGuard g(hip_device);
+    int occ = spv::main_occupancy();
+    c->blocks_per_cu = occ > 0 ? (occ < 8 ? occ : 8) : 2;
+  }
+  c->encode_block = 1024;
+  c->last = hipSuccess;
+  c->msg[0] = '\0';
+  *out = c;
+  return SPV_SUCCESS;
+}
+
+int spv_destroy(spv_ctx* ctx) {
+  delete ctx;
+  return SPV_SUCCESS;
+}
+
+const char* spv_last_hip_error(spv_ctx* ctx) { return ctx ? ctx->msg : "no context"; }
+
+int spv_set_tuning(spv_ctx* ctx, int blocks_per_cu, int encode_block) {
+  if (!ctx || blocks_per_cu < 0 || encode_block < 0 || (encode_block % 256) != 0) return SPV_ERR_INVALID_ARG;
+  if (blocks_per_cu > 0) ctx->blocks_per_cu = blocks_per_cu;
+  if (encode_block > 0) ctx->encode_block = encode_block;
+  return SPV_SUCCESS;
+}
+
+int spv_workspace_size(spv_ctx* ctx, int64_t n_modules, int64_t n_words, size_t* bytes) {
+  if (!ctx || !bytes || n_modules < 0 || n_words < 0) return SPV_ERR_INVALID_ARG;
+  *bytes = spv::make_layout(n_modules, n_words).total;
+  return SPV_SUCCESS;
+}
+
+int spv_decode(spv_ctx* ctx, const uint32_t* words, const int64_t* mod_off, int64_t n_modules, int64_t n_words,
+               uint32_t* idx_off, uint16_t* idx_op, int64_t idx_cap, spv_result* results, void* ws,
+               size_t ws_bytes, void* stream) {
+  return run_validate(ctx, words, mod_off, n_modules, n_words, idx_off, idx_op, idx_cap, results, 0, ws, ws_bytes,
+                      stream);
+}
+
+int spv_validate(spv_ctx* ctx, const uint32_t* words, const int64_t* mod_off, int64_t n_modules, int64_t n_words,
+                 uint32_t* idx_off, uint16_t* idx_op, int64_t idx_cap, spv_result* results, uint32_t option_flags,
+                 void* ws, size_t ws_bytes, void* stream) {
+  if (option_flags != 0) return SPV_ERR_INVALID_ARG;
+  return run_validate(ctx, words, mod_off, n_modules, n_words, idx_off, idx_op, idx_cap, results, 1, ws, ws_bytes,
+                      stream);
+}
+
+int spv_encode_bound(int64_t n_modules, int64_t n_records, int64_t n_opnd_words, int64_t n_string_records,
+                     int64_t n_chars, int64_t* max_words) {
+  if (!max_words || n_modules < 0 || n_records < 0 || n_opnd_words < 0 || n_string_records < 0 || n_chars < 0)
+    return SPV_ERR_INVALID_ARG;
+  *max_words = 5 * n_modules + n_records + n_opnd_words + n_string_records + n_chars / 4;
+  return SPV_SUCCESS;
+}
+
+int spv_encode_workspace_size(spv_ctx* ctx, int64_t n_modules, int64_t n_records, size_t* bytes) {
+  if (!ctx || !bytes || n_modules < 0 || n_records < 0) return SPV_ERR_INVALID_ARG;
+  *bytes = spv::make_elayout(n_modules, n_records, ctx->encode_block).total;
+  return SPV_SUCCESS;
+}
+
+int spv_encode(spv_ctx* ctx, const uint16_t* op, const int32_t* opnd_off, const uint32_t* opnd,
+               const int32_t* str_off, const uint8_t* chars, const int64_t* rec_mod_off, int64_t n_modules,
+               int64_t n_records, uint32_t version_word, uint32_t generator_word, uint32_t* words_out,
+               int64_t* word_mod_off, int64_t words_cap, uint32_t* enc_code, int64_t* enc_bad_record, void* ws,
+               size_t ws_bytes, void* stream) {
+  if (!ctx || n_modules < 0 || n_records < 0 || words_cap < 0) return SPV_ERR_INVALID_ARG;
+  if (n_modules == 0) return n_records == 0 ? SPV_SUCCESS : SPV_ERR_INVALID_ARG;
+  if (!rec_mod_off || !word_mod_off || !enc_code || !enc_bad_record || !opnd_off || !str_off)
+    return SPV_ERR_INVALID_ARG;
+  if (n_records > 0 && !op) return SPV_ERR_INVALID_ARG;
+  if (words_cap < 5 * n_modules + n_records) return SPV_ERR_CAPACITY;
+  if (words_cap > 0 && !words_out) return SPV_ERR_INVALID_ARG;
+  spv::ELayout L = spv::make_elayout(n_modules, n_records, ctx->encode_block);
+  if (!ws || ws_bytes < L.total) return SPV_ERR_WORKSPACE;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail_hip(ctx, hipErrorInvalidDevice);
+  char* base = static_cast<char*>(ws);
+  spv::EParams p;
+  p.op = op;
+  p.opnd_off = opnd_off;
+  p.opnd = opnd;
+  p.str_off = str_off;
+  p.chars = chars;
+  p.rec_mod_off = rec_mod_off;
+  p.M = n_modules;
+  p.N = n_records;
+  p.version_word = version_word;
+  p.generator_word = generator_word;
+  p.words_out = words_out;
+  p.word_mod_off = word_mod_off;
+  p.words_cap = words_cap;
+  p.enc_code = enc_code;
+  p.enc_bad = enc_bad_record;
+  p.ctrl = reinterpret_cast<uint32_t*>(base + L.ctrl);
+  p.blk = reinterpret_cast<unsigned long long*>(base + L.blk);
+  p.mod_bad = reinterpret_cast<unsigned long long*>(base + L.mod_bad);
+  p.mod_maxid = reinterpret_cast<uint32_t*>(base + L.mod_maxid);
+  p.mod_words = reinterpret_cast<int64_t*>(base + L.mod_words);
+  p.stage = nullptr;
+  p.block_records = ctx->encode_block;
+  p.n_blocks = (n_records + ctx->encode_block - 1) / ctx->encode_block;
+  int64_t grid = int64_t(ctx->n_cu) * 8;
+  if (grid > p.n_blocks) grid = p.n_blocks;
+  spv::launch_encode(p, int(grid > 0 ? grid : 1), static_cast<hipStream_t>(stream));
+  return check_launch(ctx);
+}
+
+}  // extern "C"

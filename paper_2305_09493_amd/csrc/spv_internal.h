@@ -1,0 +1,190 @@
+// Internal definitions shared by the spvgpu kernels and the C ABI.
+//
+// Batch model: module m is words[mod_off[m] .. mod_off[m+1]).  A SPIR-V
+// module is a 5-word header followed by instructions whose first word is
+// (word count << 16) | opcode (Beehive SPIR-V Toolkit paper, section "SPIR-V
+// Library" header listing and section "Parsing Operand Kinds").
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/spvgpu.h"
+
+namespace spv {
+
+// ---- tiling --------------------------------------------------------------
+constexpr int kLaneWords = 16;                    // words owned by one lane
+constexpr int kWaves = 4;                         // waves per tile block
+constexpr int kBlock = 64 * kWaves;               // 256 threads
+constexpr int kTileWords = kLaneWords * kBlock;   // 4096 words per tile
+constexpr int kListMax = 256;                     // module starts per tile window (fast path)
+constexpr int kMaxSpanTiles = 17;                 // a 65535-word instruction spans <= 17 tiles
+
+// 4-bit exit codes of a lane transfer function: 0..13 exit offset into the
+// next lane, kFar = exit not representable (long instruction), kDead = the
+// chain ends (invalid start) before leaving the lane.
+constexpr uint32_t kFar = 14, kDead = 15;
+
+// ---- tile state words (uint64, one pair per tile) --------------------------
+// A[t] (entry/exit):  bits 62..63 flag: 1 = aggregate, 2 = full.
+//   aggregate: bits 0..3 exit offset if the exit does not depend on the
+//   tile's entry (0..13), kDead (no chain leaves), or kFar meaning "depends
+//   on the entry / unknown: wait for full".
+//   full: bits 0..31 exact exit offset relative to the next tile start, or
+//   0xFFFFFFFF when no chain leaves the tile.
+//   bit 33 (both forms): the tile holds a plausible instruction start whose
+//   word count is >= 15 (a long instruction could reach past the next tile's
+//   first 14 words).
+// B[t] (instruction counts of the module open at the tile end):
+//   flag 1 = aggregate: bit 32 = a module starts inside the tile, bits 0..31
+//   = starts after the last module start (or all starts if none); flag 2 =
+//   inclusive: bits 0..31 = starts of that module up to the tile end.
+constexpr uint64_t kFlagAgg = 1ull << 62, kFlagFull = 2ull << 62, kFlagMask = 3ull << 62;
+constexpr uint64_t kFarBit = 1ull << 33;
+constexpr uint64_t kResetBit = 1ull << 32;
+constexpr uint32_t kExitDead = 0xFFFFFFFFu;
+
+// ---- per-module state in the workspace ------------------------------------
+enum : uint32_t {
+  kModOOB = 1u,
+  kModDup = 2u,
+  kModUndef = 4u,
+  kModSparse = 8u,     // IDs kept in a hash table (bound > 64 * words)
+  kModPass2 = 16u,     // undefined-ID check needs the second pass
+  kModHdrOk = 32u,
+};
+
+struct ModState {
+  unsigned long long err_key;   // (offset << 8) | code of the first failing instruction (atomicMin)
+  unsigned long long err_rank;  // (offset << 32) | instructions before it (atomicMin)
+  uint32_t flags;               // kMod* bits (atomicOr)
+  uint32_t def_count;           // distinct in-bound result IDs (atomicAdd)
+  uint32_t n_total;             // instructions of a module whose parse did not fail
+  uint32_t bound;               // header word 3
+  uint32_t hdr_code;            // header-stage code
+  uint32_t hdr_err;             // header-stage err_word
+  uint32_t pad[2];
+};
+static_assert(sizeof(ModState) == 48, "ModState layout");
+
+// ---- workspace layout ----------------------------------------------------
+struct Layout {
+  size_t ctrl, tileA, tileB, tfm, mods, idmap, total;
+};
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+inline Layout make_layout(int64_t n_modules, int64_t n_words) {
+  Layout L;
+  int64_t n_tiles = (n_words + kTileWords - 1) / kTileWords;
+  size_t off = 0;
+  L.ctrl = off;
+  off = align256(off + 256);
+  L.tileA = off;
+  off = align256(off + 8 * size_t(n_tiles + 1));
+  L.tileB = off;
+  off = align256(off + 8 * size_t(n_tiles + 1));
+  L.tfm = off;
+  off = align256(off + 4 * size_t(n_tiles + 1));
+  L.mods = off;
+  off = align256(off + sizeof(ModState) * size_t(n_modules + 1));
+  L.idmap = off;
+  off = align256(off + 8 * size_t(n_words + 1));
+  L.total = off;
+  return L;
+}
+
+// control words (uint32) at the start of the workspace
+enum { kCtlClaim = 0, kCtlClaim2 = 1, kCtlPass2 = 2, kCtlSpinErr = 3 };
+
+// Every wait on another tile's published state gives up after this many
+// polls (seconds of waiting) and flags kCtlSpinErr instead of hanging; the
+// finalize kernel then marks every result with kSpinFailCode.
+constexpr uint32_t kSpinLimit = 1u << 22;
+constexpr uint32_t kSpinFailCode = 0xDEADu;
+
+struct VParams {
+  const uint32_t* words;
+  const int64_t* mod_off;
+  int64_t M, W, n_tiles;
+  uint32_t* idx_off;
+  uint16_t* idx_op;
+  spv_result* results;
+  uint32_t* ctrl;
+  unsigned long long* tileA;
+  unsigned long long* tileB;
+  int32_t* tfm;
+  ModState* mods;
+  unsigned long long* idmap;
+  int semantic;
+  int index;
+};
+
+// Grammar entry for opcode < 256 (index 256 = any other opcode):
+//   bits 0..7  lo      smallest word count
+//   bits 8..23 n_ok    number of accepted word counts starting at lo
+//                      (1 for fixed-size instructions, 0 = opcode unknown)
+//   bits 24..27 result-ID slots (bit s-1 = operand word s is a result ID)
+//   bits 28..31 ID-use slots
+// A word w at a candidate start is a plausible instruction iff
+// (wc - lo) < n_ok (unsigned) with wc = w >> 16.
+constexpr int kOpName = 5;
+
+struct Params;  // forward
+
+void launch_plan(const VParams& p, int grid, hipStream_t s);
+void launch_main(const VParams& p, int grid, hipStream_t s);
+void launch_finalize(const VParams& p, int phase, hipStream_t s);
+void launch_pass2(const VParams& p, int grid, hipStream_t s);
+
+struct EParams {
+  const uint16_t* op;
+  const int32_t* opnd_off;
+  const uint32_t* opnd;
+  const int32_t* str_off;
+  const uint8_t* chars;
+  const int64_t* rec_mod_off;
+  int64_t M, N;  // modules, records
+  uint32_t version_word, generator_word;
+  uint32_t* words_out;
+  int64_t* word_mod_off;
+  int64_t words_cap;
+  uint32_t* enc_code;
+  int64_t* enc_bad;
+  // workspace
+  uint32_t* ctrl;
+  unsigned long long* blk;    // per-block look-back state
+  unsigned long long* mod_bad;   // per module: (record << 8) | code, atomicMin
+  uint32_t* mod_maxid;        // per module: max ID operand + 1 (atomicMax)
+  int64_t* mod_words;         // per module: optimistic start offset of its first record
+  uint32_t* stage;            // words staging for compaction
+  int64_t n_blocks;
+  int block_records;
+};
+
+struct ELayout {
+  size_t ctrl, blk, mod_bad, mod_maxid, mod_words, total;
+};
+
+inline ELayout make_elayout(int64_t n_modules, int64_t n_records, int block_records) {
+  ELayout L;
+  int64_t nb = (n_records + block_records - 1) / block_records;
+  size_t off = 0;
+  L.ctrl = off;
+  off = align256(off + 256);
+  L.blk = off;
+  off = align256(off + 8 * size_t(nb + 1));
+  L.mod_bad = off;
+  off = align256(off + 8 * size_t(n_modules + 1));
+  L.mod_maxid = off;
+  off = align256(off + 4 * size_t(n_modules + 1));
+  L.mod_words = off;
+  off = align256(off + 8 * size_t(n_modules + 1));
+  L.total = off;
+  return L;
+}
+
+void launch_encode(const EParams& p, int grid, hipStream_t s);
+
+}  // namespace spv

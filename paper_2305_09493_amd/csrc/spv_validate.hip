@@ -1,0 +1,1257 @@
+// Batched SPIR-V decode / validate kernels for gfx950 (CDNA4, wave64).
+//
+// What is computed (Beehive SPIR-V Toolkit paper, arXiv 2305.09493): the
+// disassembler's walk over a module's instructions (section "Dis/Assembler"),
+// where each instruction's first word carries its word count and opcode
+// (section "Parsing Operand Kinds"), after the 5-word header (section "SPIR-V
+// Library", header listing), and the validation the library performs before
+// storing a module (section "Validation Rules") together with the SSA rule
+// that every ID is defined once (section "Enabling Function Composition").
+//
+// How (MI355X design, see the design notes of the repository):
+//   * The batch's words are cut into tiles of 4096 words, 16 per lane, 256
+//     lanes per block; tiles ignore module boundaries.  A persistent grid
+//     claims tiles in order from an atomic counter.
+//   * Instruction-boundary recovery is pointer jumping over
+//     next(i) = i + (w[i] >> 16).  Each lane runs it backwards over its 16
+//     words once, keeping the exits of the 15 following positions as a
+//     packed 4-bit table in a 64-bit register, which yields the lane's
+//     transfer function "entry offset -> exit offset".  Chains that start on
+//     operand words die at once (implausible starts), so almost every lane's
+//     function is constant over its surviving entries; such lanes, waves and
+//     tiles publish their exit without knowing their entry, and the only
+//     serial resolution left is over runs of ambiguous lanes.
+//   * Tiles chain through a decoupled look-back (aggregate / full states in
+//     the workspace) for the exact entry and for the per-module instruction
+//     count that ranks the index entries.
+//   * Tiles with an instruction longer than 14 words on their chain, or with
+//     more than 256 module starts, take a serial per-tile path.
+//   * Result-ID define-once checks use 64-bit bitmaps (or a hash table when
+//     the bound is much larger than the module) with atomics; the
+//     undefined-ID check is skipped for modules whose result IDs cover
+//     [1, bound) (no use can then be undefined) and otherwise runs as a
+//     second pass against the completed bitmap.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "spv_internal.h"
+
+namespace spv {
+
+namespace {
+
+constexpr uint32_t kMagic = 0x07230203u;
+
+// grammar: opcode, smallest word count, count of accepted word counts,
+// result-ID slot mask, ID-use slot mask (slot s <-> bit s-1)
+struct GEnt {
+  uint16_t op;
+  uint8_t lo;
+  uint16_t nok;
+  uint8_t def;
+  uint8_t use;
+};
+__device__ __constant__ GEnt kGrammar[12] = {
+    {5, 3, 65533, 0x0, 0x1},   // OpName          U S...
+    {14, 3, 1, 0x0, 0x0},      // OpMemoryModel   L L
+    {17, 2, 1, 0x0, 0x0},      // OpCapability    L
+    {21, 4, 1, 0x1, 0x0},      // OpTypeInt       D L L
+    {43, 4, 1, 0x2, 0x1},      // OpConstant      U D L
+    {54, 5, 1, 0x2, 0x9},      // OpFunction      U D L U
+    {56, 1, 1, 0x0, 0x0},      // OpFunctionEnd
+    {61, 4, 1, 0x2, 0x5},      // OpLoad          U D U
+    {62, 3, 1, 0x0, 0x3},      // OpStore         U U
+    {128, 5, 1, 0x2, 0xD},     // OpIAdd          U D U U
+    {248, 2, 1, 0x1, 0x0},     // OpLabel         D
+    {253, 1, 1, 0x0, 0x0},     // OpReturn
+};
+
+__device__ __forceinline__ void init_table(uint32_t* tbl) {
+  for (int i = threadIdx.x; i < 257; i += blockDim.x) tbl[i] = 0;
+  __syncthreads();
+  if (threadIdx.x < 12) {
+    GEnt g = kGrammar[threadIdx.x];
+    tbl[g.op] = uint32_t(g.lo) | (uint32_t(g.nok) << 8) | (uint32_t(g.def) << 24) | (uint32_t(g.use) << 28);
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ uint32_t tbl_lookup(const uint32_t* tbl, uint32_t op) { return tbl[op < 256u ? op : 256u]; }
+__device__ __forceinline__ bool tbl_plausible(uint32_t e, uint32_t wc) {
+  return (wc - (e & 0xFFu)) < ((e >> 8) & 0xFFFFu);
+}
+
+__device__ __forceinline__ unsigned long long ld_acq(const unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_rel(unsigned long long* p, unsigned long long v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
+
+// A string operand: bytes little-endian within each word, terminated by the
+// first NUL, which must be in the last word, followed only by NUL padding.
+__device__ bool string_ok_global(const uint32_t* w, int64_t n_words) {
+  for (int64_t i = 0; i + 1 < n_words; ++i) {
+    uint32_t x = w[i];
+    if (((x - 0x01010101u) & ~x & 0x80808080u) != 0) return false;  // a NUL before the last word
+  }
+  uint32_t x = w[n_words - 1];
+  uint32_t z = (x - 0x01010101u) & ~x & 0x80808080u;  // lowest set flag marks the first NUL byte exactly
+  if (z == 0) return false;
+  int k = __builtin_ctz(z) >> 3;
+  return (x >> (8 * k)) == 0;
+}
+
+// Exact parse-stage code of a candidate start (0 if it is a valid
+// instruction).  end = end of its module (absolute word index).
+__device__ uint32_t start_code(const uint32_t* words, const uint32_t* tbl, int64_t pos, int64_t end) {
+  uint32_t w0 = words[pos];
+  uint32_t wc = w0 >> 16, op = w0 & 0xFFFFu;
+  if (wc == 0 || pos + wc > end) return SPV_E_BAD_WORD_COUNT;
+  uint32_t e = tbl_lookup(tbl, op);
+  if (((e >> 8) & 0xFFFFu) == 0) return SPV_E_UNKNOWN_OPCODE;
+  if (!tbl_plausible(e, wc)) return SPV_E_BAD_WORD_COUNT;
+  if (op == kOpName && !string_ok_global(words + pos + 2, wc - 2)) return SPV_E_BAD_STRING;
+  return 0;
+}
+
+// ---- ID sets ---------------------------------------------------------------
+// Bitmap mode: module m's bitmap is idmap[off_m .. off_m + ceil(bound/64)).
+// Hash mode: module m owns n_m 64-bit slots idmap[off_m .. off_m + n_m),
+// slot = id | (flags << 32), flags bit 0 defined, bit 1 used, 0 = empty.
+__device__ __forceinline__ uint32_t hash_slot(uint32_t v, int64_t n) {
+  return uint32_t((uint64_t(v * 2654435761u) * uint64_t(n)) >> 32);
+}
+
+// Insert id v into a hash-mode module; returns the old flag bits of v.
+__device__ uint32_t hash_insert(unsigned long long* slots, int64_t n, uint32_t v, uint32_t flag) {
+  int64_t h = hash_slot(v, n);
+  for (int64_t probe = 0; probe < n; ++probe) {
+    unsigned long long cur = __hip_atomic_load(&slots[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (uint32_t(cur) == 0u) {
+      unsigned long long prev = atomicCAS(&slots[h], 0ull, (unsigned long long)v);
+      if (prev == 0ull || uint32_t(prev) == v) cur = v;
+    }
+    if (uint32_t(cur) == v) {
+      unsigned long long old = atomicOr(&slots[h], (unsigned long long)flag << 32);
+      return uint32_t(old >> 32);
+    }
+    h = (h + 1 == n) ? 0 : h + 1;
+  }
+  return 0;  // unreachable: a module has more slots than distinct IDs
+}
+
+// ---- per-tile module list -------------------------------------------------
+struct LEnt {
+  int32_t rel;     // start - t0 (clamped to -1 below the tile)
+  int32_t mod;     // module index, -1 for the batch end
+  int64_t off;     // module start
+  int64_t end;     // module end
+  uint32_t bound;
+  uint32_t info;   // bits 0..2 header length min(5, n); bit 3 batch end; bit 4 header ok; bit 5 hash mode
+};
+constexpr uint32_t kInfoEnd = 8u, kInfoHdrOk = 16u, kInfoSparse = 32u;
+
+struct Shared {
+  uint32_t tbl[257];
+  LEnt list[kListMax];
+  int K;
+  int crowded;
+  long long t;
+  uint32_t wagg[kWaves];       // wave exit when independent of the wave entry, else 0xFF
+  uint32_t wflags[kWaves];     // bit 0: far candidate in the wave
+  uint32_t wcnt[kWaves];       // wave count aggregate (bit 31 = module start inside)
+  uint32_t E;                  // tile entry offset (exact) or kExitDead
+  uint32_t prefix;             // count of the module open at t0 before t0
+  int serial;
+  uint32_t spill[kBlock];      // role bits of words 16..19 of each lane: def | use << 4
+  uint32_t modflags[kListMax];
+  uint32_t moddef[kListMax];
+  uint32_t tail_exit[kWaves];  // exit offsets of each wave's last lane after resolution
+};
+
+// Build the list of non-empty modules overlapping [t0, t1 + 16] (wave 0).
+__device__ void build_list(Shared& S, const VParams& P, long long t, int64_t t0, int64_t t1) {
+  const int lane = lane_id();
+  int64_t m0 = P.tfm[t];
+  if (lane == 0) {
+    const ModState& ms = P.mods[m0];
+    int64_t off = P.mod_off[m0], end = P.mod_off[m0 + 1];
+    LEnt e;
+    e.rel = int32_t(off - t0 < -1 ? -1 : off - t0);
+    e.mod = int32_t(m0);
+    e.off = off;
+    e.end = end;
+    e.bound = ms.bound;
+    int64_t n = end - off;
+    e.info = uint32_t(n < 5 ? n : 5) | ((ms.flags & kModHdrOk) ? kInfoHdrOk : 0u) |
+             ((ms.flags & kModSparse) ? kInfoSparse : 0u);
+    S.list[0] = e;
+  }
+  int K = 1;
+  int crowded = 0;
+  const int64_t lim = t1 + 16;
+  for (int64_t base = m0 + 1; base < P.M; base += 64) {
+    int64_t m = base + lane;
+    bool valid = m < P.M;
+    int64_t off = valid ? P.mod_off[m] : INT64_MAX;
+    int64_t end = valid ? P.mod_off[m + 1] : INT64_MAX;
+    bool in = valid && off <= lim;
+    bool take = in && end > off;
+    uint64_t tm = __ballot(take);
+    uint64_t im = __ballot(in);
+    int pos = K + __popcll(tm & ((1ull << lane) - 1ull));
+    if (take && pos < kListMax) {
+      const ModState& ms = P.mods[m];
+      LEnt e;
+      e.rel = int32_t(off - t0);
+      e.mod = int32_t(m);
+      e.off = off;
+      e.end = end;
+      e.bound = ms.bound;
+      int64_t n = end - off;
+      e.info = uint32_t(n < 5 ? n : 5) | ((ms.flags & kModHdrOk) ? kInfoHdrOk : 0u) |
+               ((ms.flags & kModSparse) ? kInfoSparse : 0u);
+      S.list[pos] = e;
+    }
+    K += __popcll(tm);
+    if (K > kListMax - 1) {
+      crowded = 1;
+      break;
+    }
+    if (im != ~0ull) break;
+  }
+  if (!crowded && P.W <= lim) {
+    if (lane == 0) {
+      LEnt e;
+      e.rel = int32_t(P.W - t0);
+      e.mod = -1;
+      e.off = P.W;
+      e.end = P.W;
+      e.bound = 0;
+      e.info = kInfoEnd;
+      S.list[K] = e;
+    }
+    K += 1;
+  }
+  if (lane == 0) {
+    S.K = K;
+    S.crowded = crowded;
+  }
+}
+
+__device__ __forceinline__ int list_find(const Shared& S, int32_t rel) {
+  // largest j with list[j].rel <= rel (list[0].rel <= 0 <= rel)
+  int lo = 0, hi = S.K - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (S.list[mid].rel <= rel) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Count look-back: instruction starts of the module open at tile t's start
+// that lie before it.
+__device__ uint32_t count_lookback(const VParams& P, long long t) {
+  uint32_t prefix = 0;
+  long long u = t - 1;
+  uint32_t spins = 0;
+  while (u >= 0) {
+    unsigned long long st = ld_acq(&P.tileB[u]);
+    uint64_t f = st & kFlagMask;
+    if (f == 0) {
+      if (++spins > kSpinLimit) {
+        atomicOr(&P.ctrl[kCtlSpinErr], 1u);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+      continue;
+    }
+    prefix += uint32_t(st);
+    if (f == kFlagFull || (st & kResetBit)) break;
+    --u;
+  }
+  return prefix;
+}
+
+// Entry look-back (wave 0): exact entry offset of tile t, or kExitDead.
+// Returns 0xFFFFFFFE when the entry cannot be had from aggregates and the
+// full state of t-1 was awaited and found; all lanes get the same value.
+__device__ uint32_t entry_lookback(const VParams& P, long long t) {
+  const int lane = lane_id();
+  for (uint32_t spins = 0;; ++spins) {
+    if (spins > kSpinLimit) {
+      if (lane == 0) atomicOr(&P.ctrl[kCtlSpinErr], 1u);
+      return kExitDead;
+    }
+    long long u = t - 1 - lane;
+    bool real = lane < kMaxSpanTiles && u >= 0;
+    unsigned long long st = real ? ld_acq(&P.tileA[u]) : kFlagAgg;
+    unsigned long long st0 = __shfl(st, 0);
+    if ((st0 & kFlagMask) == kFlagFull) return uint32_t(st0);
+    bool pub = (st & kFlagMask) != 0;
+    if (__ballot(!pub) == 0) {
+      uint32_t X = uint32_t(st0) & 15u;
+      bool far_before = __ballot(lane >= 1 && real && (st & kFarBit)) != 0;
+      if (X != kFar && !far_before) return X == kDead ? kExitDead : X;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+}
+
+__device__ __forceinline__ uint32_t nib(uint64_t r, uint32_t k) { return uint32_t(r >> (4u * k)) & 15u; }
+
+// Apply a lane transfer function (nibble e = exit for entry e) to an entry.
+__device__ __forceinline__ uint32_t apply_fn(uint64_t F, uint32_t e) {
+  if (e == kDead) return kDead;
+  if (e >= kFar) return kFar;
+  return nib(F, e);
+}
+
+struct Lane {
+  uint32_t w[kLaneWords];
+  int64_t a;         // absolute start of the lane segment
+  int j0;            // list index of the module open at a
+  uint32_t bm;       // window [0, 32): module starts and the batch end
+  uint32_t hdr;      // bm & 0xFFFF : positions that are not instruction starts
+  uint32_t rst;      // module starts (not the batch end) in [0, 16)
+  uint64_t rstbits;  // first-instruction positions of modules starting in [0, 16)
+  uint32_t plmask;   // plausible instruction starts
+  uint32_t farmask;  // plausible starts with word count >= 15
+  uint32_t namemask; // OpName candidate starts
+  uint8_t nx[kLaneWords];   // next chain position, 40 = none
+  uint8_t roles[kLaneWords];
+  uint64_t F;        // transfer function
+  bool conv;
+  uint32_t X;
+  bool far_cand;
+};
+
+// Module-window masks of a lane.
+__device__ void lane_window(const Shared& S, Lane& L, int32_t lrel) {
+  L.j0 = (S.K == 1) ? 0 : list_find(S, lrel);
+  L.bm = 0;
+  L.rst = 0;
+  L.rstbits = 0;
+  if (S.K > 1 || S.list[0].rel >= lrel) {
+    for (int j = L.j0; j < S.K; ++j) {
+      int32_t r = S.list[j].rel - lrel;
+      if (r < 0) continue;
+      if (r >= 32) break;
+      L.bm |= 1u << r;
+      if (r < 16 && !(S.list[j].info & kInfoEnd)) {
+        L.rst |= 1u << r;
+        L.rstbits |= 1ull << (r + (S.list[j].info & 7u));
+      }
+    }
+  }
+  L.hdr = L.bm & 0xFFFFu;
+}
+
+// list index of the module that owns position p (0..15) of the lane
+__device__ __forceinline__ int lane_mod_at(const Lane& L, int p) {
+  // modules starting at positions in (0, p] of the lane advance the index
+  uint32_t below = L.rst & ((2u << p) - 1u);
+  int n = __popc(below);
+  // a module starting exactly at position 0 is already list entry j0
+  if (L.rst & 1u) n -= 1;
+  return L.j0 + n;
+}
+
+// Backward pass: plausibility of every position and the lane's transfer
+// function.  ex[p] = exit offset reached from position p (see kFar/kDead).
+template <bool kBounds>
+__device__ void lane_dp(const Shared& S, const VParams& P, Lane& L) {
+  uint64_t R = 0xEDCBA98765432100ull;  // nibble k: exit of position 15 + k
+  L.plmask = 0;
+  L.farmask = 0;
+  L.namemask = 0;
+  L.far_cand = false;
+  bool forced = false;
+  uint32_t fval = 0;
+#pragma unroll
+  for (int p = kLaneWords - 1; p >= 0; --p) {
+    uint32_t w = L.w[p];
+    uint32_t wc = w >> 16, op = w & 0xFFFFu;
+    uint32_t e = tbl_lookup(S.tbl, op);
+    bool pl = tbl_plausible(e, wc);
+    if (kBounds) {
+      // an instruction may not run past its module's end
+      uint64_t span = (wc >= 2) ? ((wc - 1 >= 40) ? ~0ull : ((1ull << (wc - 1)) - 1ull)) : 0ull;
+      pl = pl && ((((uint64_t)L.bm >> (p + 1)) & span) == 0);
+      pl = pl && !((L.hdr >> p) & 1u);
+    }
+    uint32_t val;
+    if (pl && wc >= 15u) {
+      // long instruction (only OpName can be one): keep it only if the string
+      // words that precede its last word hold no NUL byte, and the
+      // instruction stays inside its module
+      int64_t pos = L.a + p;
+      int jm = kBounds ? lane_mod_at(L, p) : L.j0;
+      int64_t end = S.list[jm].end;
+      bool ok = pos + wc <= end;
+      int64_t lim = wc - 1 < 18 ? wc - 1 : 18;
+      for (int64_t k = 2; ok && k < lim; ++k) {
+        uint32_t x = P.words[pos + k];
+        ok = ((x - 0x01010101u) & ~x & 0x80808080u) == 0;
+      }
+      pl = ok;
+      if (ok) {
+        L.farmask |= 1u << p;
+        L.far_cand = true;
+      }
+      val = ok ? kFar : kDead;
+    } else {
+      val = pl ? nib(R, wc) : kDead;
+    }
+    if (pl) L.plmask |= 1u << p;
+    if (op == kOpName) L.namemask |= 1u << p;
+    L.nx[p] = uint8_t((pl && wc < 15u) ? (p + wc) : 40u);
+    L.roles[p] = uint8_t(e >> 24);
+    if (kBounds) {
+      if ((L.hdr >> p) & 1u) {
+        // at a module start the chain restarts after the header; whatever the
+        // previous module's chain does, the lane's exit is decided from here
+        uint32_t v;
+        if (!((L.rst >> p) & 1u)) {
+          v = kDead;  // batch end: nothing follows
+        } else {
+          uint32_t hl = S.list[lane_mod_at(L, p)].info & 7u;
+          v = (p + hl < 16u) ? nib(R, hl) : (p + hl - 16u);
+        }
+        forced = true;
+        fval = v;
+        val = v;
+      } else if (forced) {
+        val = fval;
+      }
+    }
+    R = (R | val) << 4;
+  }
+  L.F = R >> 4;
+  // convergence: all entries 0..13 that survive reach the same exit
+  const uint64_t kNib14 = 0x00FFFFFFFFFFFFFFull, kOnes14 = 0x0011111111111111ull;
+  uint64_t f = L.F & kNib14;
+  if (kBounds && L.hdr) {
+    L.conv = (fval != kFar);
+    L.X = fval;
+    return;
+  }
+  uint64_t nd = ~f & kNib14;
+  uint64_t alive = (nd | (nd >> 1) | (nd >> 2) | (nd >> 3)) & kOnes14;
+  uint64_t xf = (f ^ (kOnes14 * kFar)) & kNib14;
+  uint64_t notfar = (xf | (xf >> 1) | (xf >> 2) | (xf >> 3)) & kOnes14;
+  bool anyfar = notfar != kOnes14;
+  if (alive == 0) {
+    L.conv = true;
+    L.X = kDead;
+  } else {
+    uint32_t X = uint32_t(f >> __builtin_ctzll(alive)) & 15u;
+    uint64_t xd = (f ^ (kOnes14 * X)) & kNib14;
+    uint64_t differ = (xd | (xd >> 1) | (xd >> 2) | (xd >> 3)) & kOnes14;
+    L.conv = !anyfar && (differ & alive) == 0;
+    L.X = X;
+  }
+}
+
+// Forward pass from a known entry: chain nodes of the lane.
+__device__ __forceinline__ uint64_t lane_forward(const Lane& L, uint32_t ent) {
+  uint64_t reach = (ent < 14u ? (1ull << ent) : 0ull) | L.rstbits;
+#pragma unroll
+  for (int p = 0; p < kLaneWords; ++p) reach |= ((reach >> p) & 1ull) << L.nx[p];
+  return reach;
+}
+
+__device__ __forceinline__ void report_error(ModState& ms, uint32_t rel, uint32_t code, uint32_t rank) {
+  atomicMin(&ms.err_key, ((unsigned long long)rel << 8) | code);
+  atomicMin(&ms.err_rank, ((unsigned long long)rel << 32) | rank);
+}
+
+// ID check of one ID word in module ms (bitmap or hash mode).
+__device__ __forceinline__ void id_check(const VParams& P, const LEnt& le, uint32_t v, bool is_def, uint32_t* flags,
+                                         uint32_t* defcnt) {
+  if (v == 0u || v >= le.bound) {
+    atomicOr(flags, kModOOB);
+    return;
+  }
+  unsigned long long* base = P.idmap + le.off;
+  if (le.info & kInfoSparse) {
+    uint32_t old = hash_insert(base, le.end - le.off, v, is_def ? 1u : 2u);
+    if (is_def && (old & 1u)) atomicOr(flags, kModDup);
+    return;
+  }
+  if (!is_def) return;
+  unsigned long long bit = 1ull << (v & 63u);
+  unsigned long long old = atomicOr(&base[v >> 6], bit);
+  if (old & bit) atomicOr(flags, kModDup);
+  else atomicAdd(defcnt, 1u);
+}
+
+// Serial path for one tile (thread 0): exact walk from entry E.
+template <bool kSem, bool kIdx>
+__device__ void serial_tile(Shared& S, const VParams& P, long long t, int64_t t0, int64_t t1, uint32_t E) {
+  if (threadIdx.x != 0) return;
+  int64_t m = P.tfm[t];
+  int64_t off = P.mod_off[m], end = P.mod_off[m + 1];
+  int64_t pos;
+  uint32_t cnt;
+  if (off == t0) {
+    int64_t n = end - off;
+    pos = off + (n < 5 ? n : 5);
+    cnt = 0;
+  } else {
+    pos = (E == kExitDead) ? -1 : t0 + int64_t(E);
+    cnt = count_lookback(P, t);
+  }
+  bool far = false;
+  for (;;) {
+    ModState& ms = P.mods[m];
+    bool hdr_ok = (ms.flags & kModHdrOk) != 0;
+    LEnt le;
+    le.off = off;
+    le.end = end;
+    le.bound = ms.bound;
+    le.info = (ms.flags & kModSparse) ? kInfoSparse : 0u;
+    while (pos >= 0 && pos < end && pos < t1) {
+      uint32_t code = start_code(P.words, S.tbl, pos, end);
+      uint32_t rel = uint32_t(pos - off);
+      if (code) {
+        report_error(ms, rel, code, cnt);
+        pos = -1;
+        break;
+      }
+      uint32_t w0 = P.words[pos];
+      uint32_t wc = w0 >> 16, op = w0 & 0xFFFFu;
+      if (wc >= 15u) far = true;
+      if (kIdx && hdr_ok) {
+        P.idx_off[off + cnt] = rel;
+        P.idx_op[off + cnt] = uint16_t(op);
+      }
+      if (kSem && hdr_ok) {
+        uint32_t e = tbl_lookup(S.tbl, op);
+        uint32_t dm = (e >> 24) & 0xFu, um = (e >> 28) & 0xFu;
+        for (uint32_t s = 1; s <= 4; ++s) {
+          bool d = (dm >> (s - 1)) & 1u, u = (um >> (s - 1)) & 1u;
+          if (d || u) id_check(P, le, P.words[pos + s], d, &ms.flags, &ms.def_count);
+        }
+      }
+      ++cnt;
+      pos += wc;
+    }
+    if (end <= t1) {
+      ms.n_total = cnt;  // the module's last word is in this tile
+      int64_t m2 = m + 1;
+      while (m2 < P.M && P.mod_off[m2 + 1] == P.mod_off[m2]) ++m2;
+      if (m2 >= P.M) {
+        pos = -1;
+        m = -1;
+        break;
+      }
+      m = m2;
+      off = P.mod_off[m];
+      end = P.mod_off[m + 1];
+      cnt = 0;
+      if (off >= t1) {
+        pos = -1;
+        break;
+      }
+      int64_t n = end - off;
+      pos = off + (n < 5 ? n : 5);
+      continue;
+    }
+    break;
+  }
+  uint32_t exitv = (pos >= 0) ? uint32_t(pos - t1) : kExitDead;
+  st_rel(&P.tileA[t], kFlagFull | (far ? kFarBit : 0ull) | exitv);
+  st_rel(&P.tileB[t], kFlagFull | cnt);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// plan: header stage, per-module state, tile -> module map, tile states and
+// ID-set regions cleared.
+__global__ __launch_bounds__(256) void k_plan(VParams P, int64_t chunk) {
+  const int64_t gtid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t nth = int64_t(gridDim.x) * blockDim.x;
+  if (gtid == 0) {
+    P.ctrl[kCtlClaim] = 0;
+    P.ctrl[kCtlClaim2] = 0;
+    P.ctrl[kCtlPass2] = 0;
+    P.ctrl[kCtlSpinErr] = 0;
+  }
+  for (int64_t m = gtid; m < P.M; m += nth) {
+    int64_t off = P.mod_off[m], end = P.mod_off[m + 1];
+    int64_t n = end - off;
+    const uint32_t* w = P.words + off;
+    uint32_t code = 0, err = 0xFFFFFFFFu, bound = 0;
+    if (n < 5) {
+      code = SPV_E_TRUNCATED_HEADER;
+      err = uint32_t(n);
+    } else if (w[0] != kMagic) {
+      code = SPV_E_BAD_MAGIC;
+      err = 0;
+    } else if ((w[1] & 0xFF0000FFu) != 0 || ((w[1] >> 16) & 0xFFu) != 1u || ((w[1] >> 8) & 0xFFu) > 6u) {
+      code = SPV_E_BAD_VERSION;
+      err = 1;
+    } else if (w[4] != 0) {
+      code = SPV_E_BAD_SCHEMA;
+      err = 4;
+    }
+    if (n >= 4) bound = w[3];
+    ModState s;
+    s.err_key = ~0ull;
+    s.err_rank = ~0ull;
+    s.flags = (code == 0 ? kModHdrOk : 0u) | ((uint64_t(bound) > 64ull * uint64_t(n)) ? kModSparse : 0u);
+    s.def_count = 0;
+    s.n_total = 0;
+    s.bound = bound;
+    s.hdr_code = code;
+    s.hdr_err = err;
+    s.pad[0] = s.pad[1] = 0;
+    P.mods[m] = s;
+  }
+  for (int64_t t = gtid; t < P.n_tiles; t += nth) {
+    P.tileA[t] = 0;
+    P.tileB[t] = 0;
+    // module containing word t * T: last m with mod_off[m] <= tT
+    int64_t x = t * kTileWords;
+    int64_t lo = 0, hi = P.M - 1;
+    while (lo < hi) {
+      int64_t mid = (lo + hi + 1) >> 1;
+      if (P.mod_off[mid] <= x) lo = mid;
+      else hi = mid - 1;
+    }
+    P.tfm[t] = int32_t(lo);
+  }
+  if (!P.semantic) return;
+  // clear the ID sets of header-valid modules, chunk by chunk of idmap
+  __shared__ int64_t s_m0;
+  int64_t n_chunks = (P.W + chunk - 1) / chunk;
+  for (int64_t c = blockIdx.x; c < n_chunks; c += gridDim.x) {
+    int64_t cs = c * chunk, ce = cs + chunk < P.W ? cs + chunk : P.W;
+    if (threadIdx.x == 0) {
+      int64_t lo = 0, hi = P.M - 1;
+      while (lo < hi) {
+        int64_t mid = (lo + hi + 1) >> 1;
+        if (P.mod_off[mid] <= cs) lo = mid;
+        else hi = mid - 1;
+      }
+      s_m0 = lo;
+    }
+    __syncthreads();
+    for (int64_t m = s_m0; m < P.M; ++m) {
+      int64_t off = P.mod_off[m], end = P.mod_off[m + 1];
+      if (off >= ce) break;
+      int64_t n = end - off;
+      if (n < 5) continue;
+      const uint32_t* w = P.words + off;
+      bool ok = w[0] == kMagic && (w[1] & 0xFF0000FFu) == 0 && ((w[1] >> 16) & 0xFFu) == 1u &&
+                ((w[1] >> 8) & 0xFFu) <= 6u && w[4] == 0;
+      if (!ok) continue;
+      uint64_t bound = w[3];
+      int64_t need = (bound > 64ull * uint64_t(n)) ? n : int64_t((bound + 63) / 64);
+      int64_t zs = off > cs ? off : cs, ze = off + need < ce ? off + need : ce;
+      for (int64_t i = zs + threadIdx.x; i < ze; i += blockDim.x) P.idmap[i] = 0;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// main pass: boundary recovery, parse checks, instruction index, result-ID
+// checks.
+template <bool kSem, bool kIdx>
+__global__ __launch_bounds__(kBlock) void k_main(VParams P) {
+  __shared__ Shared S;
+  init_table(S.tbl);
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6;
+  const int lane = tid & 63;
+
+  for (;;) {
+    if (tid == 0) S.t = atomicAdd(&P.ctrl[kCtlClaim], 1u);
+    __syncthreads();
+    const long long t = S.t;
+    if (t >= P.n_tiles) break;
+    const int64_t t0 = t * kTileWords;
+    const int64_t t1 = (t0 + kTileWords < P.W) ? t0 + kTileWords : P.W;
+
+    Lane L;
+    L.a = t0 + int64_t(tid) * kLaneWords;
+    // coalesced 16-byte loads of the lane's 16 words
+    if (L.a + kLaneWords <= P.W) {
+      const uint4* src = reinterpret_cast<const uint4*>(P.words + L.a);
+#pragma unroll
+      for (int i = 0; i < kLaneWords / 4; ++i) {
+        uint4 v = src[i];
+        L.w[4 * i] = v.x;
+        L.w[4 * i + 1] = v.y;
+        L.w[4 * i + 2] = v.z;
+        L.w[4 * i + 3] = v.w;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < kLaneWords; ++i) L.w[i] = (L.a + i < P.W) ? P.words[L.a + i] : 0u;
+    }
+    if (wave == 0) build_list(S, P, t, t0, t1);
+    if (tid < kListMax) {
+      S.modflags[tid] = 0;
+      S.moddef[tid] = 0;
+    }
+    if (tid == 0) S.serial = 0;
+    __syncthreads();
+
+    if (S.crowded) {
+      if (tid == 0) st_rel(&P.tileA[t], kFlagAgg | kFarBit | kFar);
+      uint32_t E = kExitDead;
+      if (wave == 0) {
+        uint32_t e = (S.list[0].rel == 0) ? kExitDead : entry_lookback(P, t);
+        E = e;
+      }
+      serial_tile<kSem, kIdx>(S, P, t, t0, t1, E);
+      __syncthreads();
+      continue;
+    }
+
+    const int32_t lrel = tid * kLaneWords;
+    lane_window(S, L, lrel);
+    const bool any_bounds = __ballot(L.bm != 0) != 0;
+    if (any_bounds) lane_dp<true>(S, P, L);
+    else lane_dp<false>(S, P, L);
+
+    // ---- wave-level resolution independent of the wave entry
+    bool known = L.conv;
+    uint32_t ex = L.conv ? L.X : 0u;
+    for (;;) {
+      uint32_t pex = __shfl_up(ex, 1);
+      bool pk = __shfl_up(known ? 1 : 0, 1) != 0 && lane > 0;
+      bool nw = !known && pk;
+      if (nw) {
+        ex = apply_fn(L.F, pex);
+        known = true;
+      }
+      if (__ballot(nw) == 0) break;
+    }
+    const bool wave_far = __ballot(L.far_cand) != 0;
+    if (lane == 63) S.wagg[wave] = known ? ex : 0xFFu;
+    if (lane == 0) S.wflags[wave] = wave_far ? 1u : 0u;
+    __syncthreads();
+
+    // ---- tile aggregate
+    if (tid == 0) {
+      bool any_far = false, serial = false;
+      for (int w = 0; w < kWaves; ++w) {
+        any_far |= (S.wflags[w] & 1u) != 0;
+        if (w >= 1 && S.wagg[w - 1] == 0xFFu) serial = true;  // a wave entry that needs the previous wave's entry
+      }
+      uint32_t X = S.wagg[kWaves - 1];
+      uint32_t agg = (serial || any_far || X == 0xFFu || X == kFar) ? kFar : X;
+      st_rel(&P.tileA[t], kFlagAgg | (any_far ? kFarBit : 0ull) | agg);
+      S.serial = serial ? 1 : 0;
+    }
+    // ---- exact tile entry
+    if (wave == 0) {
+      uint32_t E = (S.list[0].rel == 0) ? kExitDead : entry_lookback(P, t);
+      if (lane == 0) S.E = E;
+    }
+    __syncthreads();
+    const uint32_t E = S.E;
+    if (S.serial || (E != kExitDead && E >= kFar)) {
+      serial_tile<kSem, kIdx>(S, P, t, t0, t1, E);
+      __syncthreads();
+      continue;
+    }
+
+    // ---- entries of every lane
+    uint32_t Ew = (wave == 0) ? (E == kExitDead ? kDead : E) : S.wagg[wave - 1];
+    if (lane == 0 && !known) {
+      ex = apply_fn(L.F, Ew);
+      known = true;
+    }
+    for (;;) {
+      uint32_t pex = __shfl_up(ex, 1);
+      bool pk = __shfl_up(known ? 1 : 0, 1) != 0 && lane > 0;
+      bool nw = !known && pk;
+      if (nw) {
+        ex = apply_fn(L.F, pex);
+        known = true;
+      }
+      if (__ballot(nw) == 0) break;
+    }
+    uint32_t ent = __shfl_up(ex, 1);
+    if (lane == 0) ent = Ew;
+    const uint64_t reach = lane_forward(L, ent == kDead ? 99u : ent);
+    const uint32_t hdr = L.hdr;
+    const uint32_t starts = uint32_t(reach) & L.plmask & ~L.farmask & ~hdr & 0xFFFFu;
+    const uint32_t errs = uint32_t(reach) & ~L.plmask & ~hdr & 0xFFFFu;
+    const bool far_hit = (uint32_t(reach) & L.farmask & 0xFFFFu) != 0 || ent == kFar;
+    if (__syncthreads_or(far_hit)) {
+      serial_tile<kSem, kIdx>(S, P, t, t0, t1, E);
+      __syncthreads();
+      continue;
+    }
+    {
+      // the tile's exit: chain node of the last lane beyond position 15
+      if (tid == kBlock - 1) {
+        uint64_t beyond = reach >> 16;
+        uint32_t xv = beyond ? uint32_t(__builtin_ctzll(beyond)) : kExitDead;
+        if (xv != kExitDead && xv >= 24) xv = kExitDead;  // the sink
+        st_rel(&P.tileA[t], kFlagFull | (S.wflags[0] | S.wflags[1] | S.wflags[2] | S.wflags[3] ? kFarBit : 0ull) |
+                                 xv);
+      }
+    }
+
+    // ---- per-module instruction counts: segmented scan over lanes
+    const uint32_t rst = L.rst;
+    uint32_t cval;
+    if (rst) {
+      int last = 31 - __builtin_clz(rst);
+      cval = 0x80000000u | uint32_t(__popc(starts & ~((2u << last) - 1u)));
+    } else {
+      cval = uint32_t(__popc(starts));
+    }
+    uint32_t inc = cval;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      uint32_t u = __shfl_up(inc, d);
+      if (lane >= d) inc = (inc & 0x80000000u) ? inc : (inc + (u & 0x7FFFFFFFu)) | (u & 0x80000000u);
+    }
+    uint32_t excl = __shfl_up(inc, 1);
+    if (lane == 0) excl = 0;
+    if (lane == 63) S.wcnt[wave] = inc;
+    __syncthreads();
+    uint32_t wpre = 0;
+    for (int w = 0; w < wave; ++w) {
+      uint32_t v = S.wcnt[w];
+      wpre = (v & 0x80000000u) ? v : (wpre + v) | (wpre & 0x80000000u);
+    }
+    if (tid == 0) {
+      uint32_t tot = 0;
+      for (int w = 0; w < kWaves; ++w) {
+        uint32_t v = S.wcnt[w];
+        tot = (v & 0x80000000u) ? v : (tot + v) | (tot & 0x80000000u);
+      }
+      unsigned long long agg = kFlagAgg | ((tot & 0x80000000u) ? kResetBit : 0ull) | (tot & 0x7FFFFFFFu);
+      st_rel(&P.tileB[t], agg);
+      uint32_t prefix = (S.list[0].rel == 0) ? 0u : count_lookback(P, t);
+      S.prefix = prefix;
+      uint32_t incl = (tot & 0x80000000u) ? (tot & 0x7FFFFFFFu) : prefix + tot;
+      st_rel(&P.tileB[t], kFlagFull | incl);
+    }
+    __syncthreads();
+    // exclusive count before this lane for the module open at its start
+    uint32_t lex = (excl & 0x80000000u) ? excl : (wpre + excl) | (wpre & 0x80000000u);
+    const uint32_t pre = (lex & 0x80000000u) ? (lex & 0x7FFFFFFFu) : S.prefix + lex;
+
+    // rank of a start at position p: starts of its module before it
+    auto rank_at = [&](int p) -> uint32_t {
+      uint32_t below = starts & ((1u << p) - 1u);
+      uint32_t rb = rst & ((2u << p) - 1u);
+      if (rb == 0) return pre + __popc(below);
+      int r = 31 - __builtin_clz(rb);
+      return __popc(below & ~((1u << r) - 1u));
+    };
+
+    // ---- module ends owned by this lane: positions 1..16 of the window
+    {
+      uint32_t ends = (L.bm >> 1) & 0xFFFFu;  // bit k <-> end at position k+1
+      while (ends) {
+        int k = __builtin_ctz(ends);
+        ends &= ends - 1;
+        int e = k + 1;
+        // module open just before position e
+        uint32_t rb = rst & ((1u << e) - 1u);  // module starts in [0, e)
+        uint32_t below = starts & ((e >= 32) ? ~0u : ((1u << e) - 1u));
+        uint32_t c;
+        int jm;
+        if (rb == 0) {
+          c = pre + __popc(below);
+          jm = L.j0;
+        } else {
+          int r = 31 - __builtin_clz(rb);
+          c = __popc(below & ~((1u << r) - 1u));
+          jm = lane_mod_at(L, r);
+        }
+        const LEnt& le = S.list[jm];
+        if (le.mod >= 0) P.mods[le.mod].n_total = c;
+      }
+    }
+
+    // ---- parse errors: chain nodes that are not valid instructions
+    {
+      uint32_t ee = errs;
+      while (ee) {
+        int p = __builtin_ctz(ee);
+        ee &= ee - 1;
+        int jm = lane_mod_at(L, p);
+        const LEnt& le = S.list[jm];
+        int64_t pos = L.a + p;
+        if (pos >= P.W || le.mod < 0) continue;
+        uint32_t code = start_code(P.words, S.tbl, pos, le.end);
+        if (code == 0) code = SPV_E_BAD_WORD_COUNT;  // not reachable: implausible implies a failing check
+        report_error(P.mods[le.mod], uint32_t(pos - le.off), code, rank_at(p));
+      }
+      // OpName strings
+      uint32_t ns = starts & L.namemask;
+      while (ns) {
+        int p = __builtin_ctz(ns);
+        ns &= ns - 1;
+        int64_t pos = L.a + p;
+        uint32_t wc = P.words[pos] >> 16;
+        if (!string_ok_global(P.words + pos + 2, wc - 2)) {
+          int jm = lane_mod_at(L, p);
+          const LEnt& le = S.list[jm];
+          report_error(P.mods[le.mod], uint32_t(pos - le.off), SPV_E_BAD_STRING, rank_at(p));
+        }
+      }
+    }
+
+    // ---- instruction index
+    if (kIdx) {
+#pragma unroll
+      for (int p = 0; p < kLaneWords; ++p) {
+        if ((starts >> p) & 1u) {
+          int jm = lane_mod_at(L, p);
+          const LEnt& le = S.list[jm];
+          if (le.info & kInfoHdrOk) {
+            int64_t dst = le.off + rank_at(p);
+            P.idx_off[dst] = uint32_t(L.a + p - le.off);
+            P.idx_op[dst] = uint16_t(L.w[p] & 0xFFFFu);
+          }
+        }
+      }
+    }
+
+    // ---- result-ID checks
+    if (kSem) {
+      uint32_t defm = 0, usem = 0;
+#pragma unroll
+      for (int p = 0; p < kLaneWords; ++p) {
+        if ((starts >> p) & 1u) {
+          uint32_t r = L.roles[p];
+          defm |= (r & 0xFu) << (p + 1);
+          usem |= (r >> 4) << (p + 1);
+        }
+      }
+      S.spill[tid] = ((defm >> 16) & 0xFu) | (((usem >> 16) & 0xFu) << 4);
+      __syncthreads();
+      if (tid > 0) {
+        uint32_t sp = S.spill[tid - 1];
+        defm |= sp & 0xFu;
+        usem |= (sp >> 4) & 0xFu;
+      }
+      uint32_t idm = (defm | usem) & 0xFFFFu;
+#pragma unroll
+      for (int p = 0; p < kLaneWords; ++p) {
+        if ((idm >> p) & 1u) {
+          int jm = lane_mod_at(L, p);
+          const LEnt& le = S.list[jm];
+          if (le.info & kInfoHdrOk) id_check(P, le, L.w[p], (defm >> p) & 1u, &S.modflags[jm], &S.moddef[jm]);
+        }
+      }
+      // the tile's last lane also checks the words of its last instruction
+      // that lie in the next tile
+      if (tid == kBlock - 1) {
+        uint32_t sp = S.spill[tid];
+        for (int k = 0; k < 4; ++k) {
+          bool d = (sp >> k) & 1u, u = (sp >> (4 + k)) & 1u;
+          if (!(d || u)) continue;
+          int64_t pos = L.a + 16 + k;
+          int jm = lane_mod_at(L, 15);
+          const LEnt& le = S.list[jm];
+          if (le.info & kInfoHdrOk) id_check(P, le, P.words[pos], d, &S.modflags[jm], &S.moddef[jm]);
+        }
+      }
+      __syncthreads();
+      if (tid < S.K && S.list[tid].mod >= 0) {
+        ModState& ms = P.mods[S.list[tid].mod];
+        if (S.modflags[tid]) atomicOr(&ms.flags, S.modflags[tid]);
+        if (S.moddef[tid]) atomicAdd(&ms.def_count, S.moddef[tid]);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// finalize: phase 1 marks modules whose undefined-ID check needs the second
+// pass; phase 2 writes spv_result.
+__global__ __launch_bounds__(256) void k_finalize(VParams P, int phase) {
+  const int64_t gtid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t nth = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t m = gtid; m < P.M; m += nth) {
+    ModState& ms = P.mods[m];
+    if (phase == 1) {
+      if (ms.hdr_code == 0 && ms.err_key == ~0ull) {
+        bool need;
+        if (ms.flags & kModSparse) need = true;
+        else need = ms.bound > 1u && ms.def_count < ms.bound - 1u;
+        if (need) {
+          ms.flags |= kModPass2;
+          atomicAdd(&P.ctrl[kCtlPass2], 1u);
+        }
+      }
+      continue;
+    }
+    spv_result r;
+    if (ms.hdr_code != 0) {
+      r.code = ms.hdr_code;
+      r.sem_mask = 0;
+      r.err_word = ms.hdr_err;
+      r.n_inst = 0;
+    } else if (ms.err_key != ~0ull) {
+      r.code = uint32_t(ms.err_key & 0xFFu);
+      r.sem_mask = 0;
+      r.err_word = uint32_t(ms.err_key >> 8);
+      r.n_inst = uint32_t(ms.err_rank & 0xFFFFFFFFu);
+    } else {
+      uint32_t sem = P.semantic ? (ms.flags & 7u) : 0u;
+      r.code = (sem & 1u) ? SPV_E_ID_OUT_OF_BOUND : (sem & 2u) ? SPV_E_DUPLICATE_ID : (sem & 4u) ? SPV_E_UNDEFINED_ID : 0u;
+      r.sem_mask = sem;
+      r.err_word = 0xFFFFFFFFu;
+      r.n_inst = ms.n_total;
+    }
+    if (P.ctrl[kCtlSpinErr]) r.code = kSpinFailCode;
+    P.results[m] = r;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// second pass: undefined-ID check for modules marked in phase 1.
+__global__ __launch_bounds__(kBlock) void k_pass2(VParams P) {
+  __shared__ Shared S;
+  if (P.ctrl[kCtlPass2] == 0) return;
+  init_table(S.tbl);
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6;
+  const int lane = tid & 63;
+  for (;;) {
+    if (tid == 0) S.t = atomicAdd(&P.ctrl[kCtlClaim2], 1u);
+    __syncthreads();
+    const long long t = S.t;
+    if (t >= P.n_tiles) break;
+    const int64_t t0 = t * kTileWords;
+    const int64_t t1 = (t0 + kTileWords < P.W) ? t0 + kTileWords : P.W;
+    if (wave == 0) build_list(S, P, t, t0, t1);
+    __syncthreads();
+    // any module of this tile marked?
+    bool mark = false;
+    for (int j = 0; j < (S.crowded ? 0 : S.K); ++j)
+      if (S.list[j].mod >= 0 && (P.mods[S.list[j].mod].flags & kModPass2)) mark = true;
+    if (S.crowded) mark = true;
+    if (!mark) {
+      __syncthreads();
+      continue;
+    }
+    // hash-mode modules: scan their slots within this tile's word range
+    if (S.crowded) {
+      // serial fallback over the modules of the tile
+      if (tid == 0) {
+        int64_t m = P.tfm[t];
+        for (; m < P.M && P.mod_off[m] < t1; ++m) {
+          ModState& ms = P.mods[m];
+          if (!(ms.flags & kModPass2)) continue;
+          int64_t off = P.mod_off[m], end = P.mod_off[m + 1];
+          if (ms.flags & kModSparse) {
+            int64_t s0 = off > t0 ? off : t0, s1 = end < t1 ? end : t1;
+            for (int64_t i = s0; i < s1; ++i) {
+              uint32_t f = uint32_t(P.idmap[i] >> 32);
+              if ((f & 2u) && !(f & 1u)) atomicOr(&ms.flags, kModUndef);
+            }
+          }
+        }
+      }
+      __syncthreads();
+      // bitmap-mode modules of crowded tiles are walked serially below
+    } else {
+      for (int j = 0; j < S.K; ++j) {
+        const LEnt& le = S.list[j];
+        if (le.mod < 0 || !(le.info & kInfoSparse)) continue;
+        ModState& ms = P.mods[le.mod];
+        if (!(ms.flags & kModPass2)) continue;
+        int64_t s0 = le.off > t0 ? le.off : t0, s1 = le.end < t1 ? le.end : t1;
+        bool bad = false;
+        for (int64_t i = s0 + tid; i < s1; i += kBlock) {
+          uint32_t f = uint32_t(P.idmap[i] >> 32);
+          bad |= (f & 2u) && !(f & 1u);
+        }
+        if (bad) atomicOr(&ms.flags, kModUndef);
+      }
+    }
+    // bitmap-mode modules: walk the chain from the exact entry and test uses
+    uint32_t E;
+    if (S.list[0].rel == 0 || t == 0) E = kExitDead;
+    else {
+      unsigned long long st = ld_acq(&P.tileA[t - 1]);
+      E = uint32_t(st);
+    }
+    bool serial = S.crowded || (E != kExitDead && E >= kFar);
+    if (!serial) {
+      Lane L;
+      L.a = t0 + int64_t(tid) * kLaneWords;
+#pragma unroll
+      for (int i = 0; i < kLaneWords; ++i) L.w[i] = (L.a + i < P.W) ? P.words[L.a + i] : 0u;
+      lane_window(S, L, tid * kLaneWords);
+      const bool any_bounds = __ballot(L.bm != 0) != 0;
+      if (any_bounds) lane_dp<true>(S, P, L);
+      else lane_dp<false>(S, P, L);
+      bool known = L.conv;
+      uint32_t ex = L.conv ? L.X : 0u;
+      for (;;) {
+        uint32_t pex = __shfl_up(ex, 1);
+        bool pk = __shfl_up(known ? 1 : 0, 1) != 0 && lane > 0;
+        bool nw = !known && pk;
+        if (nw) {
+          ex = apply_fn(L.F, pex);
+          known = true;
+        }
+        if (__ballot(nw) == 0) break;
+      }
+      if (lane == 63) S.wagg[wave] = known ? ex : 0xFFu;
+      __syncthreads();
+      bool amb = false;
+      for (int w = 1; w < kWaves; ++w) amb |= S.wagg[w - 1] == 0xFFu;
+      if (!amb) {
+        uint32_t Ew = (wave == 0) ? (E == kExitDead ? kDead : E) : S.wagg[wave - 1];
+        if (lane == 0 && !known) {
+          ex = apply_fn(L.F, Ew);
+          known = true;
+        }
+        for (;;) {
+          uint32_t pex = __shfl_up(ex, 1);
+          bool pk = __shfl_up(known ? 1 : 0, 1) != 0 && lane > 0;
+          bool nw = !known && pk;
+          if (nw) {
+            ex = apply_fn(L.F, pex);
+            known = true;
+          }
+          if (__ballot(nw) == 0) break;
+        }
+        uint32_t ent = __shfl_up(ex, 1);
+        if (lane == 0) ent = Ew;
+        const uint64_t reach = lane_forward(L, ent == kDead ? 99u : ent);
+        const uint32_t starts = uint32_t(reach) & L.plmask & ~L.farmask & ~L.hdr & 0xFFFFu;
+        const bool far_hit = (uint32_t(reach) & L.farmask & 0xFFFFu) != 0 || ent == kFar;
+        amb = __syncthreads_or(far_hit);
+        if (!amb) {
+          uint32_t usem = 0;
+#pragma unroll
+          for (int p = 0; p < kLaneWords; ++p)
+            if ((starts >> p) & 1u) usem |= uint32_t(L.roles[p] >> 4) << (p + 1);
+          S.spill[tid] = (usem >> 16) & 0xFu;
+          __syncthreads();
+          if (tid > 0) usem |= S.spill[tid - 1];
+          auto test = [&](int jm, uint32_t v) {
+            const LEnt& le = S.list[jm];
+            if (le.mod < 0 || (le.info & kInfoSparse) || !(le.info & kInfoHdrOk)) return;
+            ModState& ms = P.mods[le.mod];
+            if (!(ms.flags & kModPass2)) return;
+            if (v == 0u || v >= le.bound) return;
+            unsigned long long word = P.idmap[le.off + (v >> 6)];
+            if (!((word >> (v & 63u)) & 1ull)) atomicOr(&ms.flags, kModUndef);
+          };
+#pragma unroll
+          for (int p = 0; p < kLaneWords; ++p)
+            if ((usem >> p) & 1u) test(lane_mod_at(L, p), L.w[p]);
+          if (tid == kBlock - 1) {
+            uint32_t sp = S.spill[tid];
+            for (int k = 0; k < 4; ++k)
+              if ((sp >> k) & 1u) test(lane_mod_at(L, 15), P.words[L.a + 16 + k]);
+          }
+        }
+      }
+      serial = amb;
+    }
+    __syncthreads();
+    if (serial && tid == 0) {
+      // exact serial walk over the tile, testing uses of marked modules
+      int64_t m = P.tfm[t];
+      int64_t off = P.mod_off[m], end = P.mod_off[m + 1];
+      int64_t pos;
+      if (off == t0) {
+        int64_t n = end - off;
+        pos = off + (n < 5 ? n : 5);
+      } else {
+        pos = (E == kExitDead) ? -1 : t0 + int64_t(E);
+      }
+      for (;;) {
+        ModState& ms = P.mods[m];
+        bool act = (ms.flags & kModPass2) && !(ms.flags & kModSparse);
+        while (pos >= 0 && pos < end && pos < t1) {
+          if (start_code(P.words, S.tbl, pos, end)) {
+            pos = -1;
+            break;
+          }
+          uint32_t w0 = P.words[pos];
+          uint32_t wc = w0 >> 16;
+          if (act) {
+            uint32_t um = (tbl_lookup(S.tbl, w0 & 0xFFFFu) >> 28) & 0xFu;
+            for (uint32_t s = 1; s <= 4; ++s) {
+              if (!((um >> (s - 1)) & 1u)) continue;
+              uint32_t v = P.words[pos + s];
+              if (v == 0u || v >= ms.bound) continue;
+              unsigned long long word = P.idmap[off + (v >> 6)];
+              if (!((word >> (v & 63u)) & 1ull)) atomicOr(&ms.flags, kModUndef);
+            }
+          }
+          pos += wc;
+        }
+        if (end <= t1) {
+          int64_t m2 = m + 1;
+          while (m2 < P.M && P.mod_off[m2 + 1] == P.mod_off[m2]) ++m2;
+          if (m2 >= P.M) break;
+          m = m2;
+          off = P.mod_off[m];
+          end = P.mod_off[m + 1];
+          if (off >= t1) break;
+          int64_t n = end - off;
+          pos = off + (n < 5 ? n : 5);
+          continue;
+        }
+        break;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+void launch_plan(const VParams& p, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_plan, dim3(grid), dim3(256), 0, s, p, int64_t(16384));
+}
+
+void launch_main(const VParams& p, int grid, hipStream_t s) {
+  if (p.semantic) {
+    if (p.index) hipLaunchKernelGGL((k_main<true, true>), dim3(grid), dim3(kBlock), 0, s, p);
+    else hipLaunchKernelGGL((k_main<true, false>), dim3(grid), dim3(kBlock), 0, s, p);
+  } else {
+    if (p.index) hipLaunchKernelGGL((k_main<false, true>), dim3(grid), dim3(kBlock), 0, s, p);
+    else hipLaunchKernelGGL((k_main<false, false>), dim3(grid), dim3(kBlock), 0, s, p);
+  }
+}
+
+void launch_finalize(const VParams& p, int phase, hipStream_t s) {
+  int64_t g = (p.M + 255) / 256;
+  int grid = int(g < 1 ? 1 : (g > 4096 ? 4096 : g));
+  hipLaunchKernelGGL(k_finalize, dim3(grid), dim3(256), 0, s, p, phase);
+}
+
+void launch_pass2(const VParams& p, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_pass2, dim3(grid), dim3(kBlock), 0, s, p);
+}
+
+}  // namespace spv
+
+namespace spv {
+int main_occupancy() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(k_main<true, true>), kBlock, 0) !=
+      hipSuccess)
+    return 0;
+  return n;
+}
+}  // namespace spv

@@ -1,0 +1,91 @@
+"""GPU parity: spv_encode through the C ABI against the CPU oracle (words,
+module offsets, status codes), plus the decode round trip."""
+import numpy as np
+import pytest
+
+import oracle
+import spvgen
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(r):
+    import torch
+    return dict(op=torch.from_numpy(r["op"].view(np.int16)).cuda(),
+                opnd_off=torch.from_numpy(r["opnd_off"]).cuda(),
+                opnd=torch.from_numpy(r["opnd"].view(np.int32)).cuda(),
+                str_off=torch.from_numpy(r["str_off"]).cuda(),
+                chars=torch.from_numpy(r["chars"]).cuda(),
+                rec_mod_off=torch.from_numpy(r["rec_mod_off"]).cuda())
+
+
+def _gpu_encode(r, **kw):
+    import torch
+    import paper_2305_09493_amd as spv
+    words, wmo, code, bad = spv.encode(**_dev(r), **kw)
+    torch.cuda.synchronize()
+    wmo = wmo.cpu().numpy()
+    return words.cpu().numpy().view(np.uint32)[:wmo[-1]], wmo, code.cpu().numpy(), bad.cpu().numpy()
+
+
+def _check(r, label, **kw):
+    print(f"[encode parity] {label} M={r['rec_mod_off'].size - 1} N={r['op'].size}", flush=True)
+    gw, gmo, gc, gb = _gpu_encode(r, **kw)
+    ow, omo, oc, ob = oracle.encode(**r, **kw)
+    assert np.array_equal(gc.astype(np.uint32), oc), label
+    assert np.array_equal(gb, ob), label
+    assert np.array_equal(gmo, omo), label
+    assert np.array_equal(gw, ow), label
+    return gw, gmo
+
+
+def test_encode_generated_modules_and_round_trip():
+    mods = [spvgen.gen_module([20, i], n) for i, n in enumerate([3, 50, 1000, 4000, 20000, 7])]
+    r = spvgen.pack_records(mods)
+    gw, gmo = _check(r, "generated")
+    b = spvgen.pack(mods)
+    assert np.array_equal(gw, b.words) and np.array_equal(gmo, b.mod_off)
+
+
+def test_encode_block_sizes():
+    import paper_2305_09493_amd as spv
+    mods = [spvgen.gen_module([21, i], 3000) for i in range(8)]
+    r = spvgen.pack_records(mods)
+    for blk in (256, 512, 2048):
+        spv.context().set_tuning(encode_block=blk)
+        _check(r, f"block {blk}")
+    spv.context().set_tuning(encode_block=1024)
+
+
+def test_encode_failures_compacted():
+    rng = np.random.default_rng(3)
+    mods = [spvgen.gen_module([22, i], int(rng.integers(3, 800))) for i in range(120)]
+    r = spvgen.pack_records(mods)
+    op = r["op"].copy()
+    opnd = r["opnd"].copy()
+    chars = r["chars"].copy()
+    n = op.size
+    for k in range(12):
+        j = int(rng.integers(0, n))
+        kind = k % 4
+        if kind == 0:
+            op[j] = 999
+        elif kind == 1 and op[j] != 5:
+            op[j] = 17 if op[j] != 17 else 14
+        elif kind == 2 and chars.size:
+            chars[int(rng.integers(0, chars.size))] = 0
+        else:
+            lo, hi = r["opnd_off"][j], r["opnd_off"][j + 1]
+            if hi > lo and op[j] in (43, 54, 61, 62, 128, 248, 21, 5):
+                opnd[lo] = 0xFFFFFFFF
+    r2 = dict(r, op=op, opnd=opnd, chars=chars)
+    _check(r2, "failures")
+
+
+def test_encode_empty_modules_and_versions():
+    mods = [spvgen.gen_module([23, i], 5) for i in range(3)]
+    r = spvgen.pack_records(mods)
+    # add empty modules at the front, middle and end
+    rmo = r["rec_mod_off"]
+    r["rec_mod_off"] = np.concatenate([[0, 0], rmo[1:2], rmo[1:2], rmo[2:], rmo[-1:]]).astype(np.int64)
+    _check(r, "empty modules", version_word=0x00010200, generator_word=32)
