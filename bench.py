@@ -1,0 +1,237 @@
+#!/usr/bin/env python
+"""Benchmark: SPIR-V words/s decoded + validated on one MI355X.
+
+Workload (timed): one synthetic module of 16M instructions (about 65M uint32
+words, 260 MB) from the seeded generator (seed 2), decoded and validated with
+the instruction index written - one step is one spv_validate call over the
+whole module (header, boundary recovery, parse checks, index, result-ID
+checks).  Inputs are resident in HBM before timing starts.
+
+Also reported on the same JSON line:
+  roofline      the dominant kernel's algorithmic bytes per launch (4 B per
+                word read + 6 B per index entry written) over its average
+                duration (HIP events on the library's stream), against
+                8 TB/s; traffic from the committed rocprofv3 counter summary
+                when it was taken on the current kernel source;
+  cpu_baseline  the CPU oracle (single thread) on the same module;
+  batched       4096 lognormal modules with 41 injected faults per launch:
+                words/s and p50 / p99 per-launch latency.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+COUNTERS = os.path.join(ROOT, "profiles", "k_main_c2_counters.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2305_09493_amd", "csrc", "spv_validate.hip")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_sha():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_from_counters(n_words, n_inst):
+    """HBM bytes per launch of the main kernel from the committed counter
+    summary (FETCH_SIZE / WRITE_SIZE scaled by a copy-kernel calibration),
+    or None when missing or taken on another kernel source or workload."""
+    try:
+        with open(COUNTERS) as f:
+            c = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if c.get("source_sha") != kernel_source_sha() or c.get("n_words") != n_words:
+        return None
+    fetch = c["fetch_kib"] * 1024.0 * c["fetch_scale"]
+    write = c["write_kib"] * 1024.0 * c["write_scale"]
+    return fetch + write
+
+
+def copy_calibration():
+    """A plain device copy of known size, for the counter calibration."""
+    import torch
+    n = 1 << 28  # 1 GiB of int32
+    src = torch.ones(n, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"copy calibration: {n * 4} bytes per copy, 3 copies")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n-inst", type=int, default=16_000_000)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched latency leg")
+    ap.add_argument("--no-check", action="store_true", help="skip the full-size parity check")
+    ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--cache", default=None, help="npy file to keep the generated module between runs")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (see the design notes on "
+              "how the path would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2305_09493_amd as spv
+    import spvgen
+
+    if args.copy_calibration:
+        copy_calibration()
+        return
+
+    dev = torch.device("cuda:0")
+    t = time.time()
+    if args.cache and os.path.exists(args.cache):
+        cw = np.load(args.cache)
+        batch = spvgen.Batch(words=cw, mod_off=np.array([0, cw.size], np.int64), modules=[])
+        log(f"loaded cached module {args.cache}")
+    else:
+        log(f"generating module: {args.n_inst} instructions")
+        batch = spvgen.config2(args.n_inst)
+        if args.cache:
+            np.save(args.cache, batch.words)
+    W = int(batch.words.size)
+    n_inst = args.n_inst
+    log(f"generated {W} words in {time.time() - t:.1f}s")
+
+    words = torch.from_numpy(batch.words.view(np.int32)).to(dev)
+    mod_off = torch.from_numpy(batch.mod_off).to(dev)
+    ctx = spv.context(0)
+    res = torch.empty((1, 4), dtype=torch.int32, device=dev)
+    idx_off = torch.empty(W, dtype=torch.int32, device=dev)
+    idx_op = torch.empty(W, dtype=torch.int16, device=dev)
+    ws = torch.empty(ctx.workspace_size(1, W), dtype=torch.uint8, device=dev)
+    out = (res, idx_off, idx_op)
+
+    def step():
+        spv.validate(words, mod_off, ctx=ctx, out=out, workspace=ws)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # timed region: K whole-path steps
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    k_ms, k_n = ctx.read_timing()
+    ctx.set_timing(False)
+    elapsed = t1 - t0
+    value = W * args.steps / elapsed
+    ms_per_step = 1e3 * elapsed / args.steps
+    k_avg_s = (k_ms / k_n) / 1e3
+    algo_bytes = 4.0 * W + 6.0 * n_inst
+    achieved = algo_bytes / k_avg_s / 1e9
+    log(f"step {ms_per_step:.3f} ms, main kernel {1e3 * k_avg_s:.3f} ms, {achieved:.0f} GB/s algorithmic")
+
+    g = res.cpu().numpy().view(np.uint32)[0]
+    checked = None
+    cpu = None
+    if not args.no_cpu or not args.no_check:
+        import oracle
+        log("CPU oracle on the same module (1 thread)")
+        t = time.perf_counter()
+        o, o_io, o_iop = oracle.validate(batch.words, batch.mod_off)
+        t_cpu = time.perf_counter() - t
+        exp = np.array([o[0][k] for k in ("code", "sem_mask", "err_word", "n_inst")], dtype=np.uint32)
+        if not args.no_check:
+            gi = idx_off.cpu().numpy().view(np.uint32)[:n_inst]
+            gop = idx_op.cpu().numpy().view(np.uint16)[:n_inst]
+            ok = (np.array_equal(g, exp) and np.array_equal(gi, o_io[:n_inst]) and
+                  np.array_equal(gop, o_iop[:n_inst]))
+            checked = bool(ok)
+            if not ok:
+                log(f"PARITY FAILURE: gpu {g} oracle {exp}")
+        if not args.no_cpu:
+            cpu = {"value": W / t_cpu, "unit": "words/s", "cores": 1, "kind": "oracle",
+                   "sample": f"the full timed module ({W} words), validate with index, one pass "
+                             f"({t_cpu:.2f} s)"}
+
+    batched = None
+    if not args.no_batched:
+        log("batched leg: 4096 lognormal modules")
+        b3 = spvgen.config3()
+        w3 = torch.from_numpy(b3.words.view(np.int32)).to(dev)
+        m3 = torch.from_numpy(b3.mod_off).to(dev)
+        M3, W3 = b3.n_modules, int(b3.words.size)
+        r3 = torch.empty((M3, 4), dtype=torch.int32, device=dev)
+        i3 = torch.empty(W3, dtype=torch.int32, device=dev)
+        p3 = torch.empty(W3, dtype=torch.int16, device=dev)
+        ws3 = torch.empty(ctx.workspace_size(M3, W3), dtype=torch.uint8, device=dev)
+        for _ in range(3):
+            spv.validate(w3, m3, ctx=ctx, out=(r3, i3, p3), workspace=ws3)
+        torch.cuda.synchronize()
+        lat = []
+        n_rep = 50
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_rep)]
+        tb0 = time.perf_counter()
+        for a, b in ev:
+            a.record()
+            spv.validate(w3, m3, ctx=ctx, out=(r3, i3, p3), workspace=ws3)
+            b.record()
+        torch.cuda.synchronize()
+        tb1 = time.perf_counter()
+        lat = np.array([a.elapsed_time(b) for a, b in ev])
+        faults = int(np.sum(r3.cpu().numpy()[:, 0] != 0))
+        batched = {"modules": M3, "words": W3, "words_per_s": W3 * n_rep / (tb1 - tb0),
+                   "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                   "modules_flagged": faults, "launches": n_rep}
+
+    traffic = traffic_from_counters(W, n_inst)
+    line = {
+        "metric": "SPIR-V words/s decoded+validated (% HBM peak); p50/p99 module latency batched",
+        "value": value,
+        "unit": "words/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic (seeded generator: 12-opcode mix, sequential result IDs, uniform backward uses)",
+        "config": {"workload": "one SPIR-V module, 16M instructions (~65M uint32 words), decode + validate "
+                               "with the instruction index", "n_inst": n_inst, "n_words": W, "modules": 1,
+                   "parallelism": "1 GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_main (decode/validate walk)", "kernel_ms": 1e3 * k_avg_s,
+                     "algorithmic_bytes": algo_bytes},
+        "cpu_baseline": cpu,
+        "hbm_fraction_whole_call": (value * (algo_bytes / W) / 1e9) / HBM_PEAK_GBS,
+        "batched": batched,
+        "parity_checked": checked,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -172,6 +172,15 @@ int spv_encode(spv_ctx *ctx, const uint16_t *op, const int32_t *opnd_off, const 
                int64_t words_cap, uint32_t *enc_code, int64_t *enc_bad_record, void *ws, size_t ws_bytes,
                void *stream);
 
+/* Measurement hook.  When enabled, every spv_decode / spv_validate call on
+ * this context records a pair of HIP events around its instruction-walk
+ * kernel (the dominant kernel) on the call's stream; spv_read_timing waits
+ * for those events, returns their summed duration in milliseconds and the
+ * number of launches since the last read, and clears them.  Not for use
+ * inside graph capture. */
+int spv_set_timing(spv_ctx *ctx, int enable);
+int spv_read_timing(spv_ctx *ctx, double *total_ms, int64_t *n_launches);
+
 #ifdef __cplusplus
 }
 #endif

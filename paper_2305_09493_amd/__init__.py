@@ -57,15 +57,19 @@ def load_library():
         lib.spv_encode_bound.argtypes = [I64, I64, I64, I64, I64, ctypes.POINTER(I64)]
         lib.spv_encode_workspace_size.argtypes = [P, I64, I64, ctypes.POINTER(SZ)]
         lib.spv_encode.argtypes = [P, P, P, P, P, P, P, I64, I64, U32, U32, P, P, I64, P, P, P, SZ, P]
+        lib.spv_set_timing.argtypes = [P, ctypes.c_int]
+        lib.spv_read_timing.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)]
         for name in ("spv_create", "spv_destroy", "spv_set_tuning", "spv_workspace_size", "spv_decode",
-                     "spv_validate", "spv_encode_bound", "spv_encode_workspace_size", "spv_encode"):
+                     "spv_validate", "spv_encode_bound", "spv_encode_workspace_size", "spv_encode",
+                     "spv_set_timing", "spv_read_timing"):
             getattr(lib, name).restype = ctypes.c_int
         _lib = lib
     return _lib
 
 
 EXPORTS = ("spv_create", "spv_destroy", "spv_last_hip_error", "spv_set_tuning", "spv_workspace_size",
-           "spv_decode", "spv_validate", "spv_encode_bound", "spv_encode_workspace_size", "spv_encode")
+           "spv_decode", "spv_validate", "spv_encode_bound", "spv_encode_workspace_size", "spv_encode",
+           "spv_set_timing", "spv_read_timing")
 
 
 def _torch():
@@ -108,6 +112,16 @@ class Context:
 
     def set_tuning(self, blocks_per_cu: int = 0, encode_block: int = 0):
         self.check(self.lib.spv_set_tuning(self.h, blocks_per_cu, encode_block), "spv_set_tuning")
+
+    def set_timing(self, enable: bool):
+        self.check(self.lib.spv_set_timing(self.h, int(bool(enable))), "spv_set_timing")
+
+    def read_timing(self):
+        """(summed milliseconds of the instruction-walk kernel, launches) since the last read."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        self.check(self.lib.spv_read_timing(self.h, ctypes.byref(ms), ctypes.byref(n)), "spv_read_timing")
+        return ms.value, n.value
 
     def workspace(self, nbytes: int):
         torch = _torch()

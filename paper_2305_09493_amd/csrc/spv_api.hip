@@ -4,6 +4,9 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <utility>
+#include <vector>
+
 #include "spv_internal.h"
 
 struct spv_ctx {
@@ -13,6 +16,9 @@ struct spv_ctx {
   int encode_block;    // records per encode block
   hipError_t last;
   char msg[256];
+  bool timing;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;  // created events
+  size_t ev_used;                                          // pairs recorded since the last read
 };
 
 namespace spv {
@@ -98,8 +104,25 @@ int run_validate(spv_ctx* ctx, const uint32_t* words, const int64_t* mod_off, in
   int64_t grid = int64_t(ctx->n_cu) * ctx->blocks_per_cu;
   if (grid > p.n_tiles) grid = p.n_tiles;
   if (grid > 0) {
+    std::pair<hipEvent_t, hipEvent_t>* ev = nullptr;
+    if (ctx->timing) {
+      if (ctx->ev_used == ctx->ev_pool.size()) {
+        std::pair<hipEvent_t, hipEvent_t> e;
+        hipError_t he = hipEventCreate(&e.first);
+        if (he == hipSuccess) he = hipEventCreate(&e.second);
+        if (he != hipSuccess) return fail_hip(ctx, he);
+        ctx->ev_pool.push_back(e);
+      }
+      ev = &ctx->ev_pool[ctx->ev_used++];
+      hipError_t he = hipEventRecord(ev->first, s);
+      if (he != hipSuccess) return fail_hip(ctx, he);
+    }
     spv::launch_main(p, int(grid), s);
     if ((r = check_launch(ctx))) return r;
+    if (ev) {
+      hipError_t he = hipEventRecord(ev->second, s);
+      if (he != hipSuccess) return fail_hip(ctx, he);
+    }
   }
   if (semantic) {
     spv::launch_finalize(p, 1, s);
@@ -137,12 +160,44 @@ int spv_create(spv_ctx** out, int hip_device) {
   c->encode_block = 1024;
   c->last = hipSuccess;
   c->msg[0] = '\0';
+  c->timing = false;
+  c->ev_used = 0;
   *out = c;
   return SPV_SUCCESS;
 }
 
 int spv_destroy(spv_ctx* ctx) {
+  if (ctx) {
+    for (auto& e : ctx->ev_pool) {
+      (void)hipEventDestroy(e.first);
+      (void)hipEventDestroy(e.second);
+    }
+  }
   delete ctx;
+  return SPV_SUCCESS;
+}
+
+int spv_set_timing(spv_ctx* ctx, int enable) {
+  if (!ctx) return SPV_ERR_INVALID_ARG;
+  ctx->timing = enable != 0;
+  ctx->ev_used = 0;
+  return SPV_SUCCESS;
+}
+
+int spv_read_timing(spv_ctx* ctx, double* total_ms, int64_t* n_launches) {
+  if (!ctx || !total_ms || !n_launches) return SPV_ERR_INVALID_ARG;
+  DeviceGuard g(ctx->device);
+  double sum = 0.0;
+  for (size_t i = 0; i < ctx->ev_used; ++i) {
+    hipError_t he = hipEventSynchronize(ctx->ev_pool[i].second);
+    float ms = 0.0f;
+    if (he == hipSuccess) he = hipEventElapsedTime(&ms, ctx->ev_pool[i].first, ctx->ev_pool[i].second);
+    if (he != hipSuccess) return fail_hip(ctx, he);
+    sum += ms;
+  }
+  *total_ms = sum;
+  *n_launches = int64_t(ctx->ev_used);
+  ctx->ev_used = 0;
   return SPV_SUCCESS;
 }
 

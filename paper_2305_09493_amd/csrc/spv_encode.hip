@@ -58,11 +58,12 @@ __device__ __forceinline__ void enc_table(uint16_t* tbl) {
   __syncthreads();
 }
 
-__device__ __forceinline__ unsigned long long ld_acq_e(const unsigned long long* p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+// block states carry their whole message: relaxed device-scope atomics
+__device__ __forceinline__ unsigned long long ld_state_e(const unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void st_rel_e(unsigned long long* p, unsigned long long v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ void st_state_e(unsigned long long* p, unsigned long long v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 constexpr unsigned long long kEAgg = 1ull << 62, kEIncl = 2ull << 62, kEMask = 3ull << 62;
@@ -150,28 +151,39 @@ __global__ __launch_bounds__(kEncThreads) void k_enc_main(EParams P) {
       if (w < wave) wpre += s_wsum[w];
       tot += s_wsum[w];
     }
-    if (tid == 0) {
-      st_rel_e(&P.blk[b], kEAgg | tot);
+    if (wave == 0) {
+      // look-back over 64 predecessor blocks per round trip
+      if (lane == 0) st_state_e(&P.blk[b], kEAgg | tot);
       unsigned long long prefix = 0;
-      long long u = b - 1;
+      long long hi = b - 1;
       uint32_t spins = 0;
-      while (u >= 0) {
-        unsigned long long st = ld_acq_e(&P.blk[u]);
+      while (hi >= 0) {
+        long long u = hi - lane;
+        unsigned long long st = (u >= 0) ? ld_state_e(&P.blk[u]) : kEIncl;
         unsigned long long f = st & kEMask;
-        if (f == 0) {
+        uint64_t stopm = __ballot(f == kEIncl);
+        uint64_t unpub = __ballot(f == 0);
+        int sl = stopm ? int(__builtin_ctzll(stopm)) : 64;
+        uint64_t need = (sl >= 63) ? ~0ull : ((2ull << sl) - 1ull);
+        if (unpub & need) {
           if (++spins > kSpinLimit) {
-            atomicOr(&P.ctrl[2], 1u);
+            if (lane == 0) atomicOr(&P.ctrl[2], 1u);
             break;
           }
           __builtin_amdgcn_s_sleep(1);
           continue;
         }
-        prefix += st & kESum;
-        if (f == kEIncl) break;
-        --u;
+        unsigned long long c = (lane <= sl) ? (st & kESum) : 0ull;
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) c += __shfl_xor(c, d);
+        prefix += c;
+        if (sl < 64) break;
+        hi -= 64;
       }
-      st_rel_e(&P.blk[b], kEIncl | (prefix + tot));
-      s_prefix = prefix;
+      if (lane == 0) {
+        st_state_e(&P.blk[b], kEIncl | (prefix + tot));
+        s_prefix = prefix;
+      }
     }
     __syncthreads();
     unsigned long long S = s_prefix + wpre + (inc - mysum);  // words of all records before rb

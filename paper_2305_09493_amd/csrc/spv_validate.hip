@@ -81,11 +81,15 @@ __device__ __forceinline__ bool tbl_plausible(uint32_t e, uint32_t wc) {
   return (wc - (e & 0xFFu)) < ((e >> 8) & 0xFFFFu);
 }
 
-__device__ __forceinline__ unsigned long long ld_acq(const unsigned long long* p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+// Tile states carry their whole message in one 64-bit word, so relaxed
+// device-scope atomics suffice: no reader depends on other data written
+// before the state.  (Acquire / release here would cost an L2 invalidate or
+// a full L2 write-back on every poll and publish.)
+__device__ __forceinline__ unsigned long long ld_state(const unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void st_rel(unsigned long long* p, unsigned long long v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ void st_state(unsigned long long* p, unsigned long long v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
@@ -102,6 +106,26 @@ __device__ bool string_ok_global(const uint32_t* w, int64_t n_words) {
   if (z == 0) return false;
   int k = __builtin_ctz(z) >> 3;
   return (x >> (8 * k)) == 0;
+}
+
+// Same rule for a string of at most 12 words (instructions of the fast
+// path): every load is issued before any test.
+__device__ __forceinline__ bool string_ok_short(const uint32_t* w, int n_words) {
+  uint32_t x[12];
+#pragma unroll
+  for (int i = 0; i < 12; ++i) x[i] = (i < n_words) ? w[i] : 0u;
+  bool ok = true;
+  uint32_t last = 0;
+#pragma unroll
+  for (int i = 0; i < 12; ++i) {
+    uint32_t z = (x[i] - 0x01010101u) & ~x[i] & 0x80808080u;
+    if (i + 1 < n_words) ok = ok && z == 0;
+    if (i + 1 == n_words) last = x[i];
+  }
+  uint32_t z = (last - 0x01010101u) & ~last & 0x80808080u;
+  if (z == 0) return false;
+  int k = __builtin_ctz(z) >> 3;
+  return ok && (last >> (8 * k)) == 0;
 }
 
 // Exact parse-stage code of a candidate start (0 if it is a valid
@@ -153,6 +177,7 @@ struct LEnt {
   uint32_t info;   // bits 0..2 header length min(5, n); bit 3 batch end; bit 4 header ok; bit 5 hash mode
 };
 constexpr uint32_t kInfoEnd = 8u, kInfoHdrOk = 16u, kInfoSparse = 32u;
+constexpr int kWinWords = 128;  // LDS window of 8192 result IDs per tile
 
 struct Shared {
   uint32_t tbl[257];
@@ -169,7 +194,13 @@ struct Shared {
   uint32_t spill[kBlock];      // role bits of words 16..19 of each lane: def | use << 4
   uint32_t modflags[kListMax];
   uint32_t moddef[kListMax];
-  uint32_t tail_exit[kWaves];  // exit offsets of each wave's last lane after resolution
+  uint32_t wst[kWaves];        // per-wave totals of instruction starts (plain scan)
+  uint32_t wref[kWaves];       // per-wave first result ID of the window module
+  int jw;                      // list index of the module whose result IDs use the LDS window
+  uint32_t slot0[kListMax];    // first staging slot of each module's starts in this tile
+  unsigned long long win[kWinWords];  // result-ID window bitmap of module jw
+  uint32_t stage[kTileWords];  // staged index entries: tile position | opcode << 16
+  uint8_t stagejm[kTileWords]; // list index of each staged entry
 };
 
 // Build the list of non-empty modules overlapping [t0, t1 + 16] (wave 0).
@@ -253,26 +284,41 @@ __device__ __forceinline__ int list_find(const Shared& S, int32_t rel) {
   return lo;
 }
 
-// Count look-back: instruction starts of the module open at tile t's start
-// that lie before it.
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
+  return v;
+}
+
+// Count look-back (called by a whole wave): instruction starts of the module
+// open at tile t's start that lie before it.  The wave reads 64 predecessor
+// states per round trip and stops at the nearest inclusive state or the
+// nearest aggregate of a tile in which a module starts.
 __device__ uint32_t count_lookback(const VParams& P, long long t) {
+  const int lane = lane_id();
   uint32_t prefix = 0;
-  long long u = t - 1;
+  long long hi = t - 1;
   uint32_t spins = 0;
-  while (u >= 0) {
-    unsigned long long st = ld_acq(&P.tileB[u]);
+  while (hi >= 0) {
+    long long u = hi - lane;
+    unsigned long long st = (u >= 0) ? ld_state(&P.tileB[u]) : kFlagFull;
     uint64_t f = st & kFlagMask;
-    if (f == 0) {
+    bool stop = f == kFlagFull || (f == kFlagAgg && (st & kResetBit));
+    uint64_t stopm = __ballot(stop);
+    uint64_t unpub = __ballot(f == 0);
+    int sl = stopm ? int(__builtin_ctzll(stopm)) : 64;
+    uint64_t need = (sl >= 63) ? ~0ull : ((2ull << sl) - 1ull);
+    if (unpub & need) {
       if (++spins > kSpinLimit) {
-        atomicOr(&P.ctrl[kCtlSpinErr], 1u);
+        if (lane == 0) atomicOr(&P.ctrl[kCtlSpinErr], 1u);
         break;
       }
       __builtin_amdgcn_s_sleep(1);
       continue;
     }
-    prefix += uint32_t(st);
-    if (f == kFlagFull || (st & kResetBit)) break;
-    --u;
+    prefix += wave_sum_u32(lane <= sl ? uint32_t(st) : 0u);
+    if (sl < 64) break;
+    hi -= 64;
   }
   return prefix;
 }
@@ -289,7 +335,7 @@ __device__ uint32_t entry_lookback(const VParams& P, long long t) {
     }
     long long u = t - 1 - lane;
     bool real = lane < kMaxSpanTiles && u >= 0;
-    unsigned long long st = real ? ld_acq(&P.tileA[u]) : kFlagAgg;
+    unsigned long long st = real ? ld_state(&P.tileA[u]) : kFlagAgg;
     unsigned long long st0 = __shfl(st, 0);
     if ((st0 & kFlagMask) == kFlagFull) return uint32_t(st0);
     bool pub = (st & kFlagMask) != 0;
@@ -493,6 +539,12 @@ __device__ __forceinline__ void id_check(const VParams& P, const LEnt& le, uint3
 // Serial path for one tile (thread 0): exact walk from entry E.
 template <bool kSem, bool kIdx>
 __device__ void serial_tile(Shared& S, const VParams& P, long long t, int64_t t0, int64_t t1, uint32_t E) {
+  // called by the whole block; wave 0 fetches the count prefix, thread 0 walks
+  if (threadIdx.x < 64) {
+    uint32_t pre = (P.mod_off[P.tfm[t]] == t0) ? 0u : count_lookback(P, t);
+    if (threadIdx.x == 0) S.prefix = pre;
+  }
+  __syncthreads();
   if (threadIdx.x != 0) return;
   int64_t m = P.tfm[t];
   int64_t off = P.mod_off[m], end = P.mod_off[m + 1];
@@ -504,7 +556,7 @@ __device__ void serial_tile(Shared& S, const VParams& P, long long t, int64_t t0
     cnt = 0;
   } else {
     pos = (E == kExitDead) ? -1 : t0 + int64_t(E);
-    cnt = count_lookback(P, t);
+    cnt = S.prefix;
   }
   bool far = false;
   for (;;) {
@@ -565,8 +617,8 @@ __device__ void serial_tile(Shared& S, const VParams& P, long long t, int64_t t0
     break;
   }
   uint32_t exitv = (pos >= 0) ? uint32_t(pos - t1) : kExitDead;
-  st_rel(&P.tileA[t], kFlagFull | (far ? kFarBit : 0ull) | exitv);
-  st_rel(&P.tileB[t], kFlagFull | cnt);
+  st_state(&P.tileA[t], kFlagFull | (far ? kFarBit : 0ull) | exitv);
+  st_state(&P.tileB[t], kFlagFull | cnt);
 }
 
 }  // namespace
@@ -702,11 +754,12 @@ __global__ __launch_bounds__(kBlock) void k_main(VParams P) {
       S.modflags[tid] = 0;
       S.moddef[tid] = 0;
     }
+    if (tid < kWinWords) S.win[tid] = 0;
     if (tid == 0) S.serial = 0;
     __syncthreads();
 
     if (S.crowded) {
-      if (tid == 0) st_rel(&P.tileA[t], kFlagAgg | kFarBit | kFar);
+      if (tid == 0) st_state(&P.tileA[t], kFlagAgg | kFarBit | kFar);
       uint32_t E = kExitDead;
       if (wave == 0) {
         uint32_t e = (S.list[0].rel == 0) ? kExitDead : entry_lookback(P, t);
@@ -717,6 +770,13 @@ __global__ __launch_bounds__(kBlock) void k_main(VParams P) {
       continue;
     }
 
+    if (tid == 0) {
+      // module whose result IDs go through the LDS window: the one at the
+      // middle of the tile, when its IDs are kept in a bitmap
+      int j = list_find(S, kTileWords / 2);
+      const LEnt& le = S.list[j];
+      S.jw = (le.mod >= 0 && (le.info & kInfoHdrOk) && !(le.info & kInfoSparse)) ? j : -1;
+    }
     const int32_t lrel = tid * kLaneWords;
     lane_window(S, L, lrel);
     const bool any_bounds = __ballot(L.bm != 0) != 0;
@@ -750,7 +810,7 @@ __global__ __launch_bounds__(kBlock) void k_main(VParams P) {
       }
       uint32_t X = S.wagg[kWaves - 1];
       uint32_t agg = (serial || any_far || X == 0xFFu || X == kFar) ? kFar : X;
-      st_rel(&P.tileA[t], kFlagAgg | (any_far ? kFarBit : 0ull) | agg);
+      st_state(&P.tileA[t], kFlagAgg | (any_far ? kFarBit : 0ull) | agg);
       S.serial = serial ? 1 : 0;
     }
     // ---- exact tile entry
@@ -800,7 +860,7 @@ __global__ __launch_bounds__(kBlock) void k_main(VParams P) {
         uint64_t beyond = reach >> 16;
         uint32_t xv = beyond ? uint32_t(__builtin_ctzll(beyond)) : kExitDead;
         if (xv != kExitDead && xv >= 24) xv = kExitDead;  // the sink
-        st_rel(&P.tileA[t], kFlagFull | (S.wflags[0] | S.wflags[1] | S.wflags[2] | S.wflags[3] ? kFarBit : 0ull) |
+        st_state(&P.tileA[t], kFlagFull | (S.wflags[0] | S.wflags[1] | S.wflags[2] | S.wflags[3] ? kFarBit : 0ull) |
                                  xv);
       }
     }
@@ -829,18 +889,22 @@ __global__ __launch_bounds__(kBlock) void k_main(VParams P) {
       uint32_t v = S.wcnt[w];
       wpre = (v & 0x80000000u) ? v : (wpre + v) | (wpre & 0x80000000u);
     }
-    if (tid == 0) {
+    if (wave == 0) {
       uint32_t tot = 0;
       for (int w = 0; w < kWaves; ++w) {
         uint32_t v = S.wcnt[w];
         tot = (v & 0x80000000u) ? v : (tot + v) | (tot & 0x80000000u);
       }
-      unsigned long long agg = kFlagAgg | ((tot & 0x80000000u) ? kResetBit : 0ull) | (tot & 0x7FFFFFFFu);
-      st_rel(&P.tileB[t], agg);
+      if (lane == 0) {
+        unsigned long long agg = kFlagAgg | ((tot & 0x80000000u) ? kResetBit : 0ull) | (tot & 0x7FFFFFFFu);
+        st_state(&P.tileB[t], agg);
+      }
       uint32_t prefix = (S.list[0].rel == 0) ? 0u : count_lookback(P, t);
-      S.prefix = prefix;
-      uint32_t incl = (tot & 0x80000000u) ? (tot & 0x7FFFFFFFu) : prefix + tot;
-      st_rel(&P.tileB[t], kFlagFull | incl);
+      if (lane == 0) {
+        S.prefix = prefix;
+        uint32_t incl = (tot & 0x80000000u) ? (tot & 0x7FFFFFFFu) : prefix + tot;
+        st_state(&P.tileB[t], kFlagFull | incl);
+      }
     }
     __syncthreads();
     // exclusive count before this lane for the module open at its start
@@ -902,7 +966,7 @@ __global__ __launch_bounds__(kBlock) void k_main(VParams P) {
         ns &= ns - 1;
         int64_t pos = L.a + p;
         uint32_t wc = P.words[pos] >> 16;
-        if (!string_ok_global(P.words + pos + 2, wc - 2)) {
+        if (!string_ok_short(P.words + pos + 2, int(wc) - 2)) {
           int jm = lane_mod_at(L, p);
           const LEnt& le = S.list[jm];
           report_error(P.mods[le.mod], uint32_t(pos - le.off), SPV_E_BAD_STRING, rank_at(p));
@@ -910,18 +974,42 @@ __global__ __launch_bounds__(kBlock) void k_main(VParams P) {
       }
     }
 
-    // ---- instruction index
+    // ---- instruction index: staged in LDS in tile order, then written with
+    // coalesced stores (a module's starts in a tile have consecutive ranks)
     if (kIdx) {
+      const uint32_t nst = __popc(starts);
+      uint32_t sinc = nst;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        uint32_t u = __shfl_up(sinc, d);
+        if (lane >= d) sinc += u;
+      }
+      if (lane == 63) S.wst[wave] = sinc;
+      __syncthreads();
+      uint32_t sbase = sinc - nst, n_slots = 0;
+      for (int w = 0; w < kWaves; ++w) {
+        if (w < wave) sbase += S.wst[w];
+        n_slots += S.wst[w];
+      }
 #pragma unroll
       for (int p = 0; p < kLaneWords; ++p) {
         if ((starts >> p) & 1u) {
+          uint32_t sl = sbase + __popc(starts & ((1u << p) - 1u));
           int jm = lane_mod_at(L, p);
-          const LEnt& le = S.list[jm];
-          if (le.info & kInfoHdrOk) {
-            int64_t dst = le.off + rank_at(p);
-            P.idx_off[dst] = uint32_t(L.a + p - le.off);
-            P.idx_op[dst] = uint16_t(L.w[p] & 0xFFFFu);
-          }
+          S.stage[sl] = uint32_t(tid * kLaneWords + p) | (L.w[p] << 16);
+          S.stagejm[sl] = uint8_t(jm);
+          if (rank_at(p) == (jm == 0 ? S.prefix : 0u)) S.slot0[jm] = sl;
+        }
+      }
+      __syncthreads();
+      for (uint32_t sl = tid; sl < n_slots; sl += kBlock) {
+        uint32_t v = S.stage[sl];
+        int jm = S.stagejm[sl];
+        const LEnt& le = S.list[jm];
+        if (le.info & kInfoHdrOk) {
+          int64_t dst = le.off + (jm == 0 ? S.prefix : 0u) + (sl - S.slot0[jm]);
+          P.idx_off[dst] = uint32_t(t0 + (v & 0xFFFFu) - le.off);
+          P.idx_op[dst] = uint16_t(v >> 16);
         }
       }
     }
@@ -945,12 +1033,42 @@ __global__ __launch_bounds__(kBlock) void k_main(VParams P) {
         usem |= (sp >> 4) & 0xFu;
       }
       uint32_t idm = (defm | usem) & 0xFFFFu;
+      // LDS window for the result IDs of module jw in this tile: anchored at
+      // the first result ID found by the lowest wave that has one
+      const int jw = S.jw;
+      {
+        const uint32_t dw = (L.rst == 0 && L.j0 == jw) ? (defm & 0xFFFFu) : 0u;
+        uint32_t first = 0;
+#pragma unroll
+        for (int p = kLaneWords - 1; p >= 0; --p)
+          if ((dw >> p) & 1u) first = L.w[p];
+        uint64_t bal = __ballot(dw != 0);
+        uint32_t ref = 0xFFFFFFFFu;
+        if (bal) ref = __shfl(first, int(__builtin_ctzll(bal)));
+        if (lane == 0) S.wref[wave] = ref;
+      }
+      __syncthreads();
+      uint32_t ref = 0xFFFFFFFFu;
+      for (int w = kWaves - 1; w >= 0; --w)
+        if (S.wref[w] != 0xFFFFFFFFu) ref = S.wref[w];
+      const bool win_on = jw >= 0 && ref != 0xFFFFFFFFu;
+      const uint32_t base64 = (ref > 2048u ? ref - 2048u : 0u) & ~63u;
 #pragma unroll
       for (int p = 0; p < kLaneWords; ++p) {
         if ((idm >> p) & 1u) {
           int jm = lane_mod_at(L, p);
           const LEnt& le = S.list[jm];
-          if (le.info & kInfoHdrOk) id_check(P, le, L.w[p], (defm >> p) & 1u, &S.modflags[jm], &S.moddef[jm]);
+          if (!(le.info & kInfoHdrOk)) continue;
+          uint32_t v = L.w[p];
+          bool is_def = (defm >> p) & 1u;
+          if (win_on && is_def && jm == jw && v != 0u && v < le.bound && v >= base64 &&
+              v - base64 < 64u * kWinWords) {
+            unsigned long long bit = 1ull << (v & 63u);
+            unsigned long long old = atomicOr(&S.win[(v - base64) >> 6], bit);
+            if (old & bit) atomicOr(&S.modflags[jm], kModDup);
+          } else {
+            id_check(P, le, v, is_def, &S.modflags[jm], &S.moddef[jm]);
+          }
         }
       }
       // the tile's last lane also checks the words of its last instruction
@@ -964,6 +1082,17 @@ __global__ __launch_bounds__(kBlock) void k_main(VParams P) {
           int jm = lane_mod_at(L, 15);
           const LEnt& le = S.list[jm];
           if (le.info & kInfoHdrOk) id_check(P, le, P.words[pos], d, &S.modflags[jm], &S.moddef[jm]);
+        }
+      }
+      __syncthreads();
+      // flush the window: one device atomic per 64 result IDs
+      if (win_on && tid < kWinWords) {
+        unsigned long long b = S.win[tid];
+        if (b) {
+          const LEnt& le = S.list[jw];
+          unsigned long long old = atomicOr(&P.idmap[le.off + (base64 >> 6) + tid], b);
+          if (old & b) atomicOr(&S.modflags[jw], kModDup);
+          atomicAdd(&S.moddef[jw], uint32_t(__popcll(b & ~old)));
         }
       }
       __syncthreads();
@@ -1086,7 +1215,7 @@ __global__ __launch_bounds__(kBlock) void k_pass2(VParams P) {
     uint32_t E;
     if (S.list[0].rel == 0 || t == 0) E = kExitDead;
     else {
-      unsigned long long st = ld_acq(&P.tileA[t - 1]);
+      unsigned long long st = ld_state(&P.tileA[t - 1]);
       E = uint32_t(st);
     }
     bool serial = S.crowded || (E != kExitDead && E >= kFar);
