@@ -75,6 +75,61 @@ def copy_calibration():
     log(f"copy calibration: {n * 4} bytes per copy, 3 copies")
 
 
+def encode_leg(ctx, dev, steps=10):
+    """Encode 10M records split into 1024 modules; records/s and output words/s."""
+    import torch
+
+    import paper_2305_09493_amd as spv
+    import spvgen
+    log("encode leg: generating 10M records in 1024 modules")
+    mods, r = spvgen.config4()
+    N = int(r["op"].size)
+    M = int(r["rec_mod_off"].size - 1)
+    d = dict(op=torch.from_numpy(r["op"].view(np.int16)).to(dev),
+             opnd_off=torch.from_numpy(r["opnd_off"]).to(dev),
+             opnd=torch.from_numpy(r["opnd"].view(np.int32)).to(dev),
+             str_off=torch.from_numpy(r["str_off"]).to(dev),
+             chars=torch.from_numpy(r["chars"]).to(dev),
+             rec_mod_off=torch.from_numpy(r["rec_mod_off"]).to(dev))
+    for _ in range(2):
+        out = spv.encode(**d, ctx=ctx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = spv.encode(**d, ctx=ctx)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    words_out = int(out[1][-1].item())
+    expect = int(sum(m.words.size for m in mods))
+    bytes_moved = (2 * N + 4 * (N + 1) + 4 * r["opnd"].size + 4 * (N + 1) + r["chars"].size) + 4 * words_out
+    return {"records": N, "modules": M, "ms_per_call": 1e3 * dt, "records_per_s": N / dt,
+            "words_out_per_s": words_out / dt, "algorithmic_GBps": bytes_moved / dt / 1e9,
+            "hbm_frac": bytes_moved / dt / 1e9 / HBM_PEAK_GBS, "output_matches_generator": words_out == expect}
+
+
+def serve_leg(args):
+    """Poisson stream of validate requests: continuous batching vs one module
+    per launch, same streams, kernels and arrival trace."""
+    import spvgen
+    from paper_2305_09493_amd.serve import run_trace
+    log(f"serving leg: pool of {args.serve_pool} modules (lognormal median 5000 instructions, max 1M)")
+    pool = [m.words for m in spvgen.serving_pool(n_pool=args.serve_pool)]
+    out = []
+    for rate in [float(x) for x in args.serve_rates.split(",")]:
+        arr = spvgen.poisson_arrivals(rate, args.serve_seconds)
+        pick = np.random.default_rng([5, int(rate)]).integers(0, len(pool), size=arr.size)
+        row = {"rate_per_s": rate, "seconds": args.serve_seconds}
+        for mode, kw in (("batched", dict(max_batch_modules=4096, n_slots=4)),
+                         ("batched_graphs", dict(max_batch_modules=4096, n_slots=4, use_graphs=True)),
+                         ("one_per_launch", dict(max_batch_modules=1, n_slots=4))):
+            log(f"  rate {rate:.0f}/s {mode}")
+            _, summ = run_trace(pool, arr, pick, **kw)
+            row[mode] = {k: summ[k] for k in ("requests", "words_per_s", "p50_ms", "p99_ms", "mean_batch",
+                                             "server_batches")}
+        out.append(row)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,6 +141,12 @@ def main():
     ap.add_argument("--no-check", action="store_true", help="skip the full-size parity check")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--cache", default=None, help="npy file to keep the generated module between runs")
+    ap.add_argument("--encode", action="store_true", help="add the encode leg (10M records, 1024 modules)")
+    ap.add_argument("--serve", action="store_true", help="add the serving leg (Poisson stream, batched vs "
+                                                         "one module per launch)")
+    ap.add_argument("--serve-rates", default="20000", help="comma-separated arrival rates for --serve")
+    ap.add_argument("--serve-seconds", type=float, default=3.0)
+    ap.add_argument("--serve-pool", type=int, default=2048)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -204,6 +265,9 @@ def main():
                    "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                    "modules_flagged": faults, "launches": n_rep}
 
+    encode = encode_leg(ctx, dev) if args.encode else None
+    serving = serve_leg(args) if args.serve else None
+
     traffic = traffic_from_counters(W, n_inst)
     line = {
         "metric": "SPIR-V words/s decoded+validated (% HBM peak); p50/p99 module latency batched",
@@ -230,6 +294,10 @@ def main():
         "batched": batched,
         "parity_checked": checked,
     }
+    if encode is not None:
+        line["encode"] = encode
+    if serving is not None:
+        line["serving"] = serving
     print(json.dumps(line), flush=True)
 
 

@@ -181,6 +181,47 @@ int spv_encode(spv_ctx *ctx, const uint16_t *op, const int32_t *opnd_off, const 
 int spv_set_timing(spv_ctx *ctx, int enable);
 int spv_read_timing(spv_ctx *ctx, double *total_ms, int64_t *n_launches);
 
+/* ---- serving: continuous batching over a stream of requests ------------
+ * A server validates one SPIR-V module per request.  Requests (host word
+ * buffers that the caller keeps alive until their completion is polled) carry
+ * an arrival time; a worker thread admits arrived requests into `n_slots`
+ * slots, each with its own stream, pinned staging and device buffers sized
+ * from device_budget_bytes (the index stays on the device).  Whenever a slot
+ * is free, every arrived request that fits joins that slot's next batch (at
+ * most max_batch_modules; 1 gives one module per launch), which is copied in,
+ * validated with spv_validate (or, with use_graphs, a HIP graph captured per
+ * padded size bucket and replayed) and whose results are copied back while
+ * other slots' batches run.  Latency = completion time - arrival time, on
+ * the server's steady clock (ns since spv_server_start).  A request larger
+ * than a slot completes with status SPV_ERR_CAPACITY.  The server keeps the
+ * context; destroy the server before the context. */
+typedef struct spv_server spv_server;
+
+typedef struct {
+  int64_t id;            /* caller's request id */
+  spv_result result;     /* the module's validation result */
+  int32_t status;        /* SPV_SUCCESS, SPV_ERR_CAPACITY or SPV_ERR_HIP */
+  int32_t pad;
+  int64_t t_arrival_ns;  /* arrival time */
+  int64_t t_done_ns;     /* time the worker saw the batch complete */
+  int64_t batch_modules; /* modules in the batch that carried this request */
+} spv_completion;
+
+int spv_server_create(spv_server **out, spv_ctx *ctx, int hip_device, size_t device_budget_bytes, int n_slots,
+                      int64_t max_batch_modules, int64_t slot_max_modules, int use_graphs);
+/* Start the worker; arrival times are relative to this call. */
+int spv_server_start(spv_server *srv);
+/* Queue n requests in arrival order: ids[i], host words[i] (n_words[i] words)
+ * arriving at t_arrival_ns[i] (NULL or negative = now). */
+int spv_server_submit(spv_server *srv, int64_t n, const int64_t *ids, const uint32_t *const *words,
+                      const int64_t *n_words, const int64_t *t_arrival_ns);
+/* Move up to max_out completions to out; *pending = submitted, not completed. */
+int spv_server_poll(spv_server *srv, spv_completion *out, int64_t max_out, int64_t *n_out, int64_t *pending);
+int spv_server_stats(spv_server *srv, int64_t *n_batches, int64_t *n_modules, int64_t *n_words, int64_t *max_batch,
+                     int64_t *slot_capacity_words);
+/* Finish all queued work, then free the server. */
+int spv_server_destroy(spv_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

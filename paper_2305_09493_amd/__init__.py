@@ -61,7 +61,8 @@ def load_library():
         lib.spv_read_timing.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)]
         for name in ("spv_create", "spv_destroy", "spv_set_tuning", "spv_workspace_size", "spv_decode",
                      "spv_validate", "spv_encode_bound", "spv_encode_workspace_size", "spv_encode",
-                     "spv_set_timing", "spv_read_timing"):
+                     "spv_set_timing", "spv_read_timing", "spv_server_create", "spv_server_start", "spv_server_submit",
+           "spv_server_poll", "spv_server_stats", "spv_server_destroy"):
             getattr(lib, name).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -69,7 +70,8 @@ def load_library():
 
 EXPORTS = ("spv_create", "spv_destroy", "spv_last_hip_error", "spv_set_tuning", "spv_workspace_size",
            "spv_decode", "spv_validate", "spv_encode_bound", "spv_encode_workspace_size", "spv_encode",
-           "spv_set_timing", "spv_read_timing")
+           "spv_set_timing", "spv_read_timing", "spv_server_create", "spv_server_start", "spv_server_submit",
+           "spv_server_poll", "spv_server_stats", "spv_server_destroy")
 
 
 def _torch():

@@ -96,7 +96,7 @@ __device__ __forceinline__ int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u,
 
 // A string operand: bytes little-endian within each word, terminated by the
 // first NUL, which must be in the last word, followed only by NUL padding.
-__device__ bool string_ok_global(const uint32_t* w, int64_t n_words) {
+__device__ __forceinline__ bool string_ok_global(const uint32_t* w, int64_t n_words) {
   for (int64_t i = 0; i + 1 < n_words; ++i) {
     uint32_t x = w[i];
     if (((x - 0x01010101u) & ~x & 0x80808080u) != 0) return false;  // a NUL before the last word
@@ -130,7 +130,7 @@ __device__ __forceinline__ bool string_ok_short(const uint32_t* w, int n_words) 
 
 // Exact parse-stage code of a candidate start (0 if it is a valid
 // instruction).  end = end of its module (absolute word index).
-__device__ uint32_t start_code(const uint32_t* words, const uint32_t* tbl, int64_t pos, int64_t end) {
+__device__ __forceinline__ uint32_t start_code(const uint32_t* words, const uint32_t* tbl, int64_t pos, int64_t end) {
   uint32_t w0 = words[pos];
   uint32_t wc = w0 >> 16, op = w0 & 0xFFFFu;
   if (wc == 0 || pos + wc > end) return SPV_E_BAD_WORD_COUNT;
@@ -150,7 +150,7 @@ __device__ __forceinline__ uint32_t hash_slot(uint32_t v, int64_t n) {
 }
 
 // Insert id v into a hash-mode module; returns the old flag bits of v.
-__device__ uint32_t hash_insert(unsigned long long* slots, int64_t n, uint32_t v, uint32_t flag) {
+__device__ __forceinline__ uint32_t hash_insert(unsigned long long* slots, int64_t n, uint32_t v, uint32_t flag) {
   int64_t h = hash_slot(v, n);
   for (int64_t probe = 0; probe < n; ++probe) {
     unsigned long long cur = __hip_atomic_load(&slots[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -204,7 +204,7 @@ struct Shared {
 };
 
 // Build the list of non-empty modules overlapping [t0, t1 + 16] (wave 0).
-__device__ void build_list(Shared& S, const VParams& P, long long t, int64_t t0, int64_t t1) {
+__device__ __forceinline__ void build_list(Shared& S, const VParams& P, long long t, int64_t t0, int64_t t1) {
   const int lane = lane_id();
   int64_t m0 = P.tfm[t];
   if (lane == 0) {
@@ -294,7 +294,7 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
 // open at tile t's start that lie before it.  The wave reads 64 predecessor
 // states per round trip and stops at the nearest inclusive state or the
 // nearest aggregate of a tile in which a module starts.
-__device__ uint32_t count_lookback(const VParams& P, long long t) {
+__device__ __forceinline__ uint32_t count_lookback(const VParams& P, long long t) {
   const int lane = lane_id();
   uint32_t prefix = 0;
   long long hi = t - 1;
@@ -326,7 +326,7 @@ __device__ uint32_t count_lookback(const VParams& P, long long t) {
 // Entry look-back (wave 0): exact entry offset of tile t, or kExitDead.
 // Returns 0xFFFFFFFE when the entry cannot be had from aggregates and the
 // full state of t-1 was awaited and found; all lanes get the same value.
-__device__ uint32_t entry_lookback(const VParams& P, long long t) {
+__device__ __forceinline__ uint32_t entry_lookback(const VParams& P, long long t) {
   const int lane = lane_id();
   for (uint32_t spins = 0;; ++spins) {
     if (spins > kSpinLimit) {
@@ -368,8 +368,8 @@ struct Lane {
   uint32_t plmask;   // plausible instruction starts
   uint32_t farmask;  // plausible starts with word count >= 15
   uint32_t namemask; // OpName candidate starts
-  uint8_t nx[kLaneWords];   // next chain position, 40 = none
-  uint8_t roles[kLaneWords];
+  uint32_t nxr[kLaneWords / 2];  // per position (16 bits): next chain position (bits 0..7, 40 = none)
+                                 // and role bits (bits 8..15: result slots | use slots << 4)
   uint64_t F;        // transfer function
   bool conv;
   uint32_t X;
@@ -377,7 +377,7 @@ struct Lane {
 };
 
 // Module-window masks of a lane.
-__device__ void lane_window(const Shared& S, Lane& L, int32_t lrel) {
+__device__ __forceinline__ void lane_window(const Shared& S, Lane& L, int32_t lrel) {
   L.j0 = (S.K == 1) ? 0 : list_find(S, lrel);
   L.bm = 0;
   L.rst = 0;
@@ -410,7 +410,7 @@ __device__ __forceinline__ int lane_mod_at(const Lane& L, int p) {
 // Backward pass: plausibility of every position and the lane's transfer
 // function.  ex[p] = exit offset reached from position p (see kFar/kDead).
 template <bool kBounds>
-__device__ void lane_dp(const Shared& S, const VParams& P, Lane& L) {
+__device__ __forceinline__ void lane_dp(const Shared& S, const VParams& P, Lane& L) {
   uint64_t R = 0xEDCBA98765432100ull;  // nibble k: exit of position 15 + k
   L.plmask = 0;
   L.farmask = 0;
@@ -455,8 +455,11 @@ __device__ void lane_dp(const Shared& S, const VParams& P, Lane& L) {
     }
     if (pl) L.plmask |= 1u << p;
     if (op == kOpName) L.namemask |= 1u << p;
-    L.nx[p] = uint8_t((pl && wc < 15u) ? (p + wc) : 40u);
-    L.roles[p] = uint8_t(e >> 24);
+    {
+      uint32_t packed = ((pl && wc < 15u) ? (p + wc) : 40u) | ((e >> 24) << 8);
+      if (p & 1) L.nxr[p >> 1] = packed << 16;
+      else L.nxr[p >> 1] |= packed;
+    }
     if (kBounds) {
       if ((L.hdr >> p) & 1u) {
         // at a module start the chain restarts after the header; whatever the
@@ -507,7 +510,7 @@ __device__ void lane_dp(const Shared& S, const VParams& P, Lane& L) {
 __device__ __forceinline__ uint64_t lane_forward(const Lane& L, uint32_t ent) {
   uint64_t reach = (ent < 14u ? (1ull << ent) : 0ull) | L.rstbits;
 #pragma unroll
-  for (int p = 0; p < kLaneWords; ++p) reach |= ((reach >> p) & 1ull) << L.nx[p];
+  for (int p = 0; p < kLaneWords; ++p) reach |= ((reach >> p) & 1ull) << ((L.nxr[p >> 1] >> (16 * (p & 1))) & 0xFFu);
   return reach;
 }
 
@@ -538,7 +541,7 @@ __device__ __forceinline__ void id_check(const VParams& P, const LEnt& le, uint3
 
 // Serial path for one tile (thread 0): exact walk from entry E.
 template <bool kSem, bool kIdx>
-__device__ void serial_tile(Shared& S, const VParams& P, long long t, int64_t t0, int64_t t1, uint32_t E) {
+__device__ __forceinline__ void serial_tile(Shared& S, const VParams& P, long long t, int64_t t0, int64_t t1, uint32_t E) {
   // called by the whole block; wave 0 fetches the count prefix, thread 0 walks
   if (threadIdx.x < 64) {
     uint32_t pre = (P.mod_off[P.tfm[t]] == t0) ? 0u : count_lookback(P, t);
@@ -758,16 +761,16 @@ __global__ __launch_bounds__(kBlock) void k_main(VParams P) {
     if (tid == 0) S.serial = 0;
     __syncthreads();
 
+    // Every way into the serial path leaves the block below with go_serial
+    // set (one call site keeps a single inlined copy of it).
+    uint32_t serialE = kExitDead;
+    bool go_serial = false;
+    do {
     if (S.crowded) {
       if (tid == 0) st_state(&P.tileA[t], kFlagAgg | kFarBit | kFar);
-      uint32_t E = kExitDead;
-      if (wave == 0) {
-        uint32_t e = (S.list[0].rel == 0) ? kExitDead : entry_lookback(P, t);
-        E = e;
-      }
-      serial_tile<kSem, kIdx>(S, P, t, t0, t1, E);
-      __syncthreads();
-      continue;
+      if (wave == 0) serialE = (S.list[0].rel == 0) ? kExitDead : entry_lookback(P, t);
+      go_serial = true;
+      break;
     }
 
     if (tid == 0) {
@@ -821,9 +824,9 @@ __global__ __launch_bounds__(kBlock) void k_main(VParams P) {
     __syncthreads();
     const uint32_t E = S.E;
     if (S.serial || (E != kExitDead && E >= kFar)) {
-      serial_tile<kSem, kIdx>(S, P, t, t0, t1, E);
-      __syncthreads();
-      continue;
+      serialE = E;
+      go_serial = true;
+      break;
     }
 
     // ---- entries of every lane
@@ -850,9 +853,9 @@ __global__ __launch_bounds__(kBlock) void k_main(VParams P) {
     const uint32_t errs = uint32_t(reach) & ~L.plmask & ~hdr & 0xFFFFu;
     const bool far_hit = (uint32_t(reach) & L.farmask & 0xFFFFu) != 0 || ent == kFar;
     if (__syncthreads_or(far_hit)) {
-      serial_tile<kSem, kIdx>(S, P, t, t0, t1, E);
-      __syncthreads();
-      continue;
+      serialE = E;
+      go_serial = true;
+      break;
     }
     {
       // the tile's exit: chain node of the last lane beyond position 15
@@ -991,14 +994,29 @@ __global__ __launch_bounds__(kBlock) void k_main(VParams P) {
         if (w < wave) sbase += S.wst[w];
         n_slots += S.wst[w];
       }
+      if (L.rst == 0) {
+        const int j0 = L.j0;
+        const uint32_t base_rank = (j0 == 0 ? S.prefix : 0u);
 #pragma unroll
-      for (int p = 0; p < kLaneWords; ++p) {
-        if ((starts >> p) & 1u) {
-          uint32_t sl = sbase + __popc(starts & ((1u << p) - 1u));
-          int jm = lane_mod_at(L, p);
-          S.stage[sl] = uint32_t(tid * kLaneWords + p) | (L.w[p] << 16);
-          S.stagejm[sl] = uint8_t(jm);
-          if (rank_at(p) == (jm == 0 ? S.prefix : 0u)) S.slot0[jm] = sl;
+        for (int p = 0; p < kLaneWords; ++p) {
+          if ((starts >> p) & 1u) {
+            uint32_t below = __popc(starts & ((1u << p) - 1u));
+            uint32_t sl = sbase + below;
+            S.stage[sl] = uint32_t(tid * kLaneWords + p) | (L.w[p] << 16);
+            S.stagejm[sl] = uint8_t(j0);
+            if (pre + below == base_rank) S.slot0[j0] = sl;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int p = 0; p < kLaneWords; ++p) {
+          if ((starts >> p) & 1u) {
+            uint32_t sl = sbase + __popc(starts & ((1u << p) - 1u));
+            int jm = lane_mod_at(L, p);
+            S.stage[sl] = uint32_t(tid * kLaneWords + p) | (L.w[p] << 16);
+            S.stagejm[sl] = uint8_t(jm);
+            if (rank_at(p) == (jm == 0 ? S.prefix : 0u)) S.slot0[jm] = sl;
+          }
         }
       }
       __syncthreads();
@@ -1020,7 +1038,7 @@ __global__ __launch_bounds__(kBlock) void k_main(VParams P) {
 #pragma unroll
       for (int p = 0; p < kLaneWords; ++p) {
         if ((starts >> p) & 1u) {
-          uint32_t r = L.roles[p];
+          uint32_t r = (L.nxr[p >> 1] >> (16 * (p & 1) + 8)) & 0xFFu;
           defm |= (r & 0xFu) << (p + 1);
           usem |= (r >> 4) << (p + 1);
         }
@@ -1053,22 +1071,58 @@ __global__ __launch_bounds__(kBlock) void k_main(VParams P) {
         if (S.wref[w] != 0xFFFFFFFFu) ref = S.wref[w];
       const bool win_on = jw >= 0 && ref != 0xFFFFFFFFu;
       const uint32_t base64 = (ref > 2048u ? ref - 2048u : 0u) & ~63u;
+      // Hot loop: bound check and LDS-window insertion for lanes whose whole
+      // segment belongs to one module; every other ID word (result outside
+      // the window, hash-mode module, lanes with a module start) is collected
+      // in `rare` and handled below from memory.
+      uint32_t rare = 0;
+      if (L.rst == 0) {
+        const int j0 = L.j0;
+        const uint32_t info = S.list[j0].info, bound = S.list[j0].bound;
+        if ((info & kInfoHdrOk) && !(info & kInfoSparse)) {
+          const bool win_here = win_on && j0 == jw;
+          bool oob = false, dup = false;
 #pragma unroll
-      for (int p = 0; p < kLaneWords; ++p) {
-        if ((idm >> p) & 1u) {
-          int jm = lane_mod_at(L, p);
-          const LEnt& le = S.list[jm];
-          if (!(le.info & kInfoHdrOk)) continue;
-          uint32_t v = L.w[p];
-          bool is_def = (defm >> p) & 1u;
-          if (win_on && is_def && jm == jw && v != 0u && v < le.bound && v >= base64 &&
-              v - base64 < 64u * kWinWords) {
-            unsigned long long bit = 1ull << (v & 63u);
-            unsigned long long old = atomicOr(&S.win[(v - base64) >> 6], bit);
-            if (old & bit) atomicOr(&S.modflags[jm], kModDup);
-          } else {
-            id_check(P, le, v, is_def, &S.modflags[jm], &S.moddef[jm]);
+          for (int p = 0; p < kLaneWords; ++p) {
+            if ((idm >> p) & 1u) {
+              uint32_t v = L.w[p];
+              bool is_def = (defm >> p) & 1u;
+              bool bad = v == 0u || v >= bound;
+              oob |= bad;
+              bool in_win = win_here && v - base64 < 64u * kWinWords && v >= base64;
+              if (!bad && is_def) {
+                if (in_win) {
+                  unsigned long long bit = 1ull << (v & 63u);
+                  unsigned long long old = atomicOr(&S.win[(v - base64) >> 6], bit);
+                  dup |= (old & bit) != 0;
+                } else {
+                  rare |= 1u << p;
+                }
+              }
+            }
           }
+          if (oob || dup) atomicOr(&S.modflags[j0], (oob ? kModOOB : 0u) | (dup ? kModDup : 0u));
+        } else if (info & kInfoHdrOk) {
+          rare = idm;
+        }
+      } else {
+        rare = idm;
+      }
+      while (rare) {
+        int p = __builtin_ctz(rare);
+        rare &= rare - 1;
+        int jm = lane_mod_at(L, p);
+        const LEnt& le = S.list[jm];
+        if (!(le.info & kInfoHdrOk)) continue;
+        uint32_t v = P.words[L.a + p];
+        bool is_def = (defm >> p) & 1u;
+        if (win_on && is_def && jm == jw && v != 0u && v < le.bound && v >= base64 &&
+            v - base64 < 64u * kWinWords) {
+          unsigned long long bit = 1ull << (v & 63u);
+          unsigned long long old = atomicOr(&S.win[(v - base64) >> 6], bit);
+          if (old & bit) atomicOr(&S.modflags[jm], kModDup);
+        } else {
+          id_check(P, le, v, is_def, &S.modflags[jm], &S.moddef[jm]);
         }
       }
       // the tile's last lane also checks the words of its last instruction
@@ -1102,6 +1156,8 @@ __global__ __launch_bounds__(kBlock) void k_main(VParams P) {
         if (S.moddef[tid]) atomicAdd(&ms.def_count, S.moddef[tid]);
       }
     }
+    } while (false);
+    if (go_serial) serial_tile<kSem, kIdx>(S, P, t, t0, t1, serialE);
     __syncthreads();
   }
 }
@@ -1270,7 +1326,7 @@ __global__ __launch_bounds__(kBlock) void k_pass2(VParams P) {
           uint32_t usem = 0;
 #pragma unroll
           for (int p = 0; p < kLaneWords; ++p)
-            if ((starts >> p) & 1u) usem |= uint32_t(L.roles[p] >> 4) << (p + 1);
+            if ((starts >> p) & 1u) usem |= ((L.nxr[p >> 1] >> (16 * (p & 1) + 12)) & 0xFu) << (p + 1);
           S.spill[tid] = (usem >> 16) & 0xFu;
           __syncthreads();
           if (tid > 0) usem |= S.spill[tid - 1];
