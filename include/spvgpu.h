@@ -112,6 +112,8 @@ const char *spv_last_hip_error(spv_ctx *ctx);
  * persistent grid of the decode/validate kernel; encode_block sets the
  * records per encode block (a multiple of 256). */
 int spv_set_tuning(spv_ctx *ctx, int blocks_per_cu, int encode_block);
+/* Current launch tuning of the context. */
+int spv_get_tuning(spv_ctx *ctx, int *blocks_per_cu, int *encode_block);
 
 /* Bytes of workspace that spv_decode / spv_validate need for a batch of
  * n_modules modules and n_words words (about 8 bytes per word plus small

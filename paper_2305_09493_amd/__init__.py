@@ -58,10 +58,11 @@ def load_library():
         lib.spv_encode_workspace_size.argtypes = [P, I64, I64, ctypes.POINTER(SZ)]
         lib.spv_encode.argtypes = [P, P, P, P, P, P, P, I64, I64, U32, U32, P, P, I64, P, P, P, SZ, P]
         lib.spv_set_timing.argtypes = [P, ctypes.c_int]
+        lib.spv_get_tuning.argtypes = [P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
         lib.spv_read_timing.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)]
         for name in ("spv_create", "spv_destroy", "spv_set_tuning", "spv_workspace_size", "spv_decode",
                      "spv_validate", "spv_encode_bound", "spv_encode_workspace_size", "spv_encode",
-                     "spv_set_timing", "spv_read_timing", "spv_server_create", "spv_server_start", "spv_server_submit",
+                     "spv_set_timing", "spv_read_timing", "spv_get_tuning", "spv_server_create", "spv_server_start", "spv_server_submit",
            "spv_server_poll", "spv_server_stats", "spv_server_destroy"):
             getattr(lib, name).restype = ctypes.c_int
         _lib = lib
@@ -70,7 +71,7 @@ def load_library():
 
 EXPORTS = ("spv_create", "spv_destroy", "spv_last_hip_error", "spv_set_tuning", "spv_workspace_size",
            "spv_decode", "spv_validate", "spv_encode_bound", "spv_encode_workspace_size", "spv_encode",
-           "spv_set_timing", "spv_read_timing", "spv_server_create", "spv_server_start", "spv_server_submit",
+           "spv_set_timing", "spv_read_timing", "spv_get_tuning", "spv_server_create", "spv_server_start", "spv_server_submit",
            "spv_server_poll", "spv_server_stats", "spv_server_destroy")
 
 
@@ -114,6 +115,12 @@ class Context:
 
     def set_tuning(self, blocks_per_cu: int = 0, encode_block: int = 0):
         self.check(self.lib.spv_set_tuning(self.h, blocks_per_cu, encode_block), "spv_set_tuning")
+
+    def get_tuning(self):
+        """(blocks_per_cu, encode_block) currently in use."""
+        a, b = ctypes.c_int(), ctypes.c_int()
+        self.check(self.lib.spv_get_tuning(self.h, ctypes.byref(a), ctypes.byref(b)), "spv_get_tuning")
+        return a.value, b.value
 
     def set_timing(self, enable: bool):
         self.check(self.lib.spv_set_timing(self.h, int(bool(enable))), "spv_set_timing")

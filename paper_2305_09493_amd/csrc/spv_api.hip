@@ -210,6 +210,13 @@ int spv_set_tuning(spv_ctx* ctx, int blocks_per_cu, int encode_block) {
   return SPV_SUCCESS;
 }
 
+int spv_get_tuning(spv_ctx* ctx, int* blocks_per_cu, int* encode_block) {
+  if (!ctx || !blocks_per_cu || !encode_block) return SPV_ERR_INVALID_ARG;
+  *blocks_per_cu = ctx->blocks_per_cu;
+  *encode_block = ctx->encode_block;
+  return SPV_SUCCESS;
+}
+
 int spv_workspace_size(spv_ctx* ctx, int64_t n_modules, int64_t n_words, size_t* bytes) {
   if (!ctx || !bytes || n_modules < 0 || n_words < 0) return SPV_ERR_INVALID_ARG;
   *bytes = spv::make_layout(n_modules, n_words).total;

@@ -18,7 +18,7 @@ constexpr int kLaneWords = 16;                    // words owned by one lane
 constexpr int kWaves = 4;                         // waves per tile block
 constexpr int kBlock = 64 * kWaves;               // 256 threads
 constexpr int kTileWords = kLaneWords * kBlock;   // 4096 words per tile
-constexpr int kListMax = 256;                     // module starts per tile window (fast path)
+constexpr int kListMax = 64;                      // module starts per tile window (fast path)
 constexpr int kMaxSpanTiles = 17;                 // a 65535-word instruction spans <= 17 tiles
 
 // 4-bit exit codes of a lane transfer function: 0..13 exit offset into the

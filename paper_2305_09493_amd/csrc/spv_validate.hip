@@ -178,34 +178,50 @@ struct LEnt {
 };
 constexpr uint32_t kInfoEnd = 8u, kInfoHdrOk = 16u, kInfoSparse = 32u;
 constexpr int kWinWords = 128;  // LDS window of 8192 result IDs per tile
+constexpr int kTwTail = 32;     // words past the tile end kept in LDS
 
 struct Shared {
+  uint32_t tw[kTileWords + kTwTail] __attribute__((aligned(16)));  // the tile's words (+ the next 32)
+  uint32_t stage[kTileWords];  // staged index entries: tile position | opcode << 16
   uint32_t tbl[257];
   LEnt list[kListMax];
   int K;
   int crowded;
   long long t;
+  long long tnext;             // next tile, claimed ahead
   uint32_t wagg[kWaves];       // wave exit when independent of the wave entry, else 0xFF
   uint32_t wflags[kWaves];     // bit 0: far candidate in the wave
   uint32_t wcnt[kWaves];       // wave count aggregate (bit 31 = module start inside)
+  uint32_t wst[kWaves];        // per-wave totals of instruction starts (plain scan)
+  uint32_t wref[kWaves];       // per-wave first result ID of the window module
   uint32_t E;                  // tile entry offset (exact) or kExitDead
   uint32_t prefix;             // count of the module open at t0 before t0
   int serial;
+  int jw;                      // list index of the module whose result IDs use the LDS window
   uint32_t spill[kBlock];      // role bits of words 16..19 of each lane: def | use << 4
   uint32_t modflags[kListMax];
   uint32_t moddef[kListMax];
-  uint32_t wst[kWaves];        // per-wave totals of instruction starts (plain scan)
-  uint32_t wref[kWaves];       // per-wave first result ID of the window module
-  int jw;                      // list index of the module whose result IDs use the LDS window
   uint32_t slot0[kListMax];    // first staging slot of each module's starts in this tile
   unsigned long long win[kWinWords];  // result-ID window bitmap of module jw
-  uint32_t stage[kTileWords];  // staged index entries: tile position | opcode << 16
-  uint8_t stagejm[kTileWords]; // list index of each staged entry
+  LEnt cache;                  // module containing the previous tile's start
+  int cache_ok;
 };
 
 // Build the list of non-empty modules overlapping [t0, t1 + 16] (wave 0).
 __device__ __forceinline__ void build_list(Shared& S, const VParams& P, long long t, int64_t t0, int64_t t1) {
   const int lane = lane_id();
+  // a block's previous tile may have lain in a module that also covers this
+  // whole tile window: then that module is the only list entry
+  if (S.cache_ok && S.cache.off <= t0 && S.cache.end > t1 + 16) {
+    if (lane == 0) {
+      LEnt e = S.cache;
+      e.rel = int32_t(e.off - t0 < -1 ? -1 : e.off - t0);
+      S.list[0] = e;
+      S.K = 1;
+      S.crowded = 0;
+    }
+    return;
+  }
   int64_t m0 = P.tfm[t];
   if (lane == 0) {
     const ModState& ms = P.mods[m0];
@@ -270,6 +286,8 @@ __device__ __forceinline__ void build_list(Shared& S, const VParams& P, long lon
   if (lane == 0) {
     S.K = K;
     S.crowded = crowded;
+    S.cache = S.list[0];
+    S.cache_ok = 1;
   }
 }
 
@@ -364,12 +382,11 @@ struct Lane {
   uint32_t bm;       // window [0, 32): module starts and the batch end
   uint32_t hdr;      // bm & 0xFFFF : positions that are not instruction starts
   uint32_t rst;      // module starts (not the batch end) in [0, 16)
-  uint64_t rstbits;  // first-instruction positions of modules starting in [0, 16)
+  uint32_t rstbits;  // first-instruction positions of modules starting in [0, 16)
   uint32_t plmask;   // plausible instruction starts
   uint32_t farmask;  // plausible starts with word count >= 15
   uint32_t namemask; // OpName candidate starts
-  uint32_t nxr[kLaneWords / 2];  // per position (16 bits): next chain position (bits 0..7, 40 = none)
-                                 // and role bits (bits 8..15: result slots | use slots << 4)
+  uint32_t rolep[kLaneWords / 4];  // role bits per position (8 bits: result slots | use slots << 4)
   uint64_t F;        // transfer function
   bool conv;
   uint32_t X;
@@ -390,7 +407,7 @@ __device__ __forceinline__ void lane_window(const Shared& S, Lane& L, int32_t lr
       L.bm |= 1u << r;
       if (r < 16 && !(S.list[j].info & kInfoEnd)) {
         L.rst |= 1u << r;
-        L.rstbits |= 1ull << (r + (S.list[j].info & 7u));
+        L.rstbits |= 1u << (r + (S.list[j].info & 7u));
       }
     }
   }
@@ -411,55 +428,67 @@ __device__ __forceinline__ int lane_mod_at(const Lane& L, int p) {
 // function.  ex[p] = exit offset reached from position p (see kFar/kDead).
 template <bool kBounds>
 __device__ __forceinline__ void lane_dp(const Shared& S, const VParams& P, Lane& L) {
-  uint64_t R = 0xEDCBA98765432100ull;  // nibble k: exit of position 15 + k
-  L.plmask = 0;
-  L.farmask = 0;
-  L.namemask = 0;
-  L.far_cand = false;
-  bool forced = false;
-  uint32_t fval = 0;
+  // pass 1: every position as a candidate instruction start; all grammar
+  // lookups are issued before any is used
+  uint32_t e[kLaneWords];
 #pragma unroll
-  for (int p = kLaneWords - 1; p >= 0; --p) {
-    uint32_t w = L.w[p];
-    uint32_t wc = w >> 16, op = w & 0xFFFFu;
-    uint32_t e = tbl_lookup(S.tbl, op);
-    bool pl = tbl_plausible(e, wc);
+  for (int p = 0; p < kLaneWords; ++p) e[p] = tbl_lookup(S.tbl, L.w[p] & 0xFFFFu);
+  uint32_t pl_m = 0, far_m = 0, name_m = 0;
+#pragma unroll
+  for (int p = 0; p < kLaneWords; ++p) {
+    const uint32_t wc = L.w[p] >> 16;
+    bool pl = tbl_plausible(e[p], wc);
     if (kBounds) {
-      // an instruction may not run past its module's end
+      // an instruction may not run past its module's end, and module starts
+      // (headers) and the batch end are not instruction starts
       uint64_t span = (wc >= 2) ? ((wc - 1 >= 40) ? ~0ull : ((1ull << (wc - 1)) - 1ull)) : 0ull;
       pl = pl && ((((uint64_t)L.bm >> (p + 1)) & span) == 0);
       pl = pl && !((L.hdr >> p) & 1u);
     }
-    uint32_t val;
-    if (pl && wc >= 15u) {
-      // long instruction (only OpName can be one): keep it only if the string
-      // words that precede its last word hold no NUL byte, and the
-      // instruction stays inside its module
-      int64_t pos = L.a + p;
-      int jm = kBounds ? lane_mod_at(L, p) : L.j0;
-      int64_t end = S.list[jm].end;
-      bool ok = pos + wc <= end;
-      int64_t lim = wc - 1 < 18 ? wc - 1 : 18;
-      for (int64_t k = 2; ok && k < lim; ++k) {
+    pl_m |= uint32_t(pl) << p;
+    far_m |= uint32_t(pl && wc >= 15u) << p;
+    name_m |= uint32_t((L.w[p] & 0xFFFFu) == uint32_t(kOpName)) << p;
+    if ((p & 3) == 0) L.rolep[p >> 2] = 0;
+    L.rolep[p >> 2] |= (e[p] >> 24) << (8 * (p & 3));
+  }
+  // long instructions (only OpName can be one; rare): kept only when they
+  // stay inside their module and the string words before the last hold no
+  // NUL byte
+  L.far_cand = false;
+  if (far_m) {
+    uint32_t fm = far_m;
+    while (fm) {
+      const int p = __builtin_ctz(fm);
+      fm &= fm - 1;
+      const int64_t pos = L.a + p;
+      const uint32_t wc = P.words[pos] >> 16;
+      const int jm = kBounds ? lane_mod_at(L, p) : L.j0;
+      bool ok = pos + int64_t(wc) <= S.list[jm].end;
+      const uint32_t lim = wc - 1 < 18u ? wc - 1 : 18u;
+      for (uint32_t k = 2; ok && k < lim; ++k) {
         uint32_t x = P.words[pos + k];
         ok = ((x - 0x01010101u) & ~x & 0x80808080u) == 0;
       }
-      pl = ok;
-      if (ok) {
-        L.farmask |= 1u << p;
-        L.far_cand = true;
+      if (!ok) {
+        pl_m &= ~(1u << p);
+        far_m &= ~(1u << p);
       }
-      val = ok ? kFar : kDead;
-    } else {
-      val = pl ? nib(R, wc) : kDead;
     }
-    if (pl) L.plmask |= 1u << p;
-    if (op == kOpName) L.namemask |= 1u << p;
-    {
-      uint32_t packed = ((pl && wc < 15u) ? (p + wc) : 40u) | ((e >> 24) << 8);
-      if (p & 1) L.nxr[p >> 1] = packed << 16;
-      else L.nxr[p >> 1] |= packed;
-    }
+    L.far_cand = far_m != 0;
+  }
+  L.plmask = pl_m;
+  L.farmask = far_m;
+  L.namemask = name_m;
+  // pass 2: exits, backwards; nibble k of R is the exit of position p + k
+  uint64_t R = 0xEDCBA98765432100ull;  // positions 16..30: exit offsets 0..13, 14 = far
+  bool forced = false;
+  uint32_t fval = 0;
+#pragma unroll
+  for (int p = kLaneWords - 1; p >= 0; --p) {
+    const uint32_t wc = L.w[p] >> 16;
+    const bool pl = (pl_m >> p) & 1u;
+    const bool far = (far_m >> p) & 1u;
+    uint32_t val = pl ? (far ? kFar : nib(R, wc & 15u)) : kDead;
     if (kBounds) {
       if ((L.hdr >> p) & 1u) {
         // at a module start the chain restarts after the header; whatever the
@@ -506,11 +535,16 @@ __device__ __forceinline__ void lane_dp(const Shared& S, const VParams& P, Lane&
   }
 }
 
-// Forward pass from a known entry: chain nodes of the lane.
-__device__ __forceinline__ uint64_t lane_forward(const Lane& L, uint32_t ent) {
-  uint64_t reach = (ent < 14u ? (1ull << ent) : 0ull) | L.rstbits;
+// Forward pass from a known entry: chain nodes of the lane (bit p = position
+// p of the window; bit 31 is the sink of dead or long chains).
+__device__ __forceinline__ uint32_t lane_forward(const Lane& L, uint32_t ent) {
+  uint32_t reach = (ent < 14u ? (1u << ent) : 0u) | L.rstbits;
+  const uint32_t okm = L.plmask & ~L.farmask;
 #pragma unroll
-  for (int p = 0; p < kLaneWords; ++p) reach |= ((reach >> p) & 1ull) << ((L.nxr[p >> 1] >> (16 * (p & 1))) & 0xFFu);
+  for (int p = 0; p < kLaneWords; ++p) {
+    uint32_t go = ((reach & okm) >> p) & 1u;
+    reach |= go << (p + (L.w[p] >> 16));
+  }
   return reach;
 }
 
@@ -722,22 +756,48 @@ __global__ __launch_bounds__(256) void k_plan(VParams P, int64_t chunk) {
 template <bool kSem, bool kIdx>
 __global__ __launch_bounds__(kBlock) void k_main(VParams P) {
   __shared__ Shared S;
+  if (threadIdx.x == 0) S.cache_ok = 0;
   init_table(S.tbl);
   const int tid = threadIdx.x;
   const int wave = tid >> 6;
   const int lane = tid & 63;
+  // the first tile is claimed here, each later one near the end of the tile
+  // before it
+  if (tid == 0) S.tnext = atomicAdd(&P.ctrl[kCtlClaim], 1u);
+  // result-ID window flush of the previous tile: issued at its end, its
+  // returned words are examined at the start of the next tile
+  unsigned long long fl_old = 0, fl_bits = 0;
+  int64_t fl_mod = -1;
 
   for (;;) {
-    if (tid == 0) S.t = atomicAdd(&P.ctrl[kCtlClaim], 1u);
     __syncthreads();
-    const long long t = S.t;
+    const long long t = S.tnext;
+    // fold the previous tile's flush into its module's state
+    if (kSem && fl_mod >= 0) {
+      uint32_t cnt = 0;
+      bool dup = false;
+      if (tid < kWinWords && fl_bits) {
+        dup = (fl_old & fl_bits) != 0;
+        cnt = uint32_t(__popcll(fl_bits & ~fl_old));
+      }
+      if (wave < kWinWords / 64) {
+        cnt = wave_sum_u32(cnt);
+        bool d = __ballot(dup) != 0;
+        if (lane == 0) {
+          if (cnt) atomicAdd(&P.mods[fl_mod].def_count, cnt);
+          if (d) atomicOr(&P.mods[fl_mod].flags, kModDup);
+        }
+      }
+      fl_mod = -1;
+    }
     if (t >= P.n_tiles) break;
     const int64_t t0 = t * kTileWords;
     const int64_t t1 = (t0 + kTileWords < P.W) ? t0 + kTileWords : P.W;
 
     Lane L;
     L.a = t0 + int64_t(tid) * kLaneWords;
-    // coalesced 16-byte loads of the lane's 16 words
+    // coalesced 16-byte loads of the lane's 16 words, kept in registers and
+    // in LDS (strings and rare paths read the LDS copy)
     if (L.a + kLaneWords <= P.W) {
       const uint4* src = reinterpret_cast<const uint4*>(P.words + L.a);
 #pragma unroll
@@ -747,17 +807,23 @@ __global__ __launch_bounds__(kBlock) void k_main(VParams P) {
         L.w[4 * i + 1] = v.y;
         L.w[4 * i + 2] = v.z;
         L.w[4 * i + 3] = v.w;
+        *reinterpret_cast<uint4*>(&S.tw[tid * kLaneWords + 4 * i]) = v;
       }
     } else {
 #pragma unroll
-      for (int i = 0; i < kLaneWords; ++i) L.w[i] = (L.a + i < P.W) ? P.words[L.a + i] : 0u;
+      for (int i = 0; i < kLaneWords; ++i) {
+        L.w[i] = (L.a + i < P.W) ? P.words[L.a + i] : 0u;
+        S.tw[tid * kLaneWords + i] = L.w[i];
+      }
     }
+    if (tid < kTwTail) S.tw[kTileWords + tid] = (t1 + tid < P.W) ? P.words[t1 + tid] : 0u;
     if (wave == 0) build_list(S, P, t, t0, t1);
     if (tid < kListMax) {
       S.modflags[tid] = 0;
       S.moddef[tid] = 0;
+      S.slot0[tid] = 0xFFFFFFFFu;
     }
-    if (tid < kWinWords) S.win[tid] = 0;
+    if (kSem && tid < kWinWords) S.win[tid] = 0;
     if (tid == 0) S.serial = 0;
     __syncthreads();
 
@@ -847,7 +913,7 @@ __global__ __launch_bounds__(kBlock) void k_main(VParams P) {
     }
     uint32_t ent = __shfl_up(ex, 1);
     if (lane == 0) ent = Ew;
-    const uint64_t reach = lane_forward(L, ent == kDead ? 99u : ent);
+    const uint32_t reach = lane_forward(L, ent == kDead ? 99u : ent);
     const uint32_t hdr = L.hdr;
     const uint32_t starts = uint32_t(reach) & L.plmask & ~L.farmask & ~hdr & 0xFFFFu;
     const uint32_t errs = uint32_t(reach) & ~L.plmask & ~hdr & 0xFFFFu;
@@ -857,178 +923,89 @@ __global__ __launch_bounds__(kBlock) void k_main(VParams P) {
       go_serial = true;
       break;
     }
-    {
+    if (tid == kBlock - 1) {
       // the tile's exit: chain node of the last lane beyond position 15
-      if (tid == kBlock - 1) {
-        uint64_t beyond = reach >> 16;
-        uint32_t xv = beyond ? uint32_t(__builtin_ctzll(beyond)) : kExitDead;
-        if (xv != kExitDead && xv >= 24) xv = kExitDead;  // the sink
-        st_state(&P.tileA[t], kFlagFull | (S.wflags[0] | S.wflags[1] | S.wflags[2] | S.wflags[3] ? kFarBit : 0ull) |
-                                 xv);
-      }
+      uint32_t beyond = reach >> 16;
+      uint32_t xv = beyond ? uint32_t(__builtin_ctz(beyond)) : kExitDead;
+      if (xv != kExitDead && xv >= 14u) xv = kExitDead;  // the sink
+      st_state(&P.tileA[t],
+               kFlagFull | (S.wflags[0] | S.wflags[1] | S.wflags[2] | S.wflags[3] ? kFarBit : 0ull) | xv);
     }
 
-    // ---- per-module instruction counts: segmented scan over lanes
+    // ---- scans over lanes: per-module instruction counts (segmented by
+    // module starts) and tile-local staging slots (plain)
     const uint32_t rst = L.rst;
+    const uint32_t nst = __popc(starts);
     uint32_t cval;
     if (rst) {
       int last = 31 - __builtin_clz(rst);
       cval = 0x80000000u | uint32_t(__popc(starts & ~((2u << last) - 1u)));
     } else {
-      cval = uint32_t(__popc(starts));
+      cval = nst;
     }
-    uint32_t inc = cval;
+    uint32_t inc = cval, sinc = nst;
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
       uint32_t u = __shfl_up(inc, d);
-      if (lane >= d) inc = (inc & 0x80000000u) ? inc : (inc + (u & 0x7FFFFFFFu)) | (u & 0x80000000u);
+      uint32_t us = __shfl_up(sinc, d);
+      if (lane >= d) {
+        inc = (inc & 0x80000000u) ? inc : (inc + (u & 0x7FFFFFFFu)) | (u & 0x80000000u);
+        sinc += us;
+      }
     }
     uint32_t excl = __shfl_up(inc, 1);
     if (lane == 0) excl = 0;
-    if (lane == 63) S.wcnt[wave] = inc;
+    if (lane == 63) {
+      S.wcnt[wave] = inc;
+      S.wst[wave] = sinc;
+    }
     __syncthreads();
-    uint32_t wpre = 0;
-    for (int w = 0; w < wave; ++w) {
+    uint32_t wpre = 0, tot = 0, sbase = sinc - nst, n_slots = 0;
+    for (int w = 0; w < kWaves; ++w) {
       uint32_t v = S.wcnt[w];
-      wpre = (v & 0x80000000u) ? v : (wpre + v) | (wpre & 0x80000000u);
+      if (w < wave) {
+        wpre = (v & 0x80000000u) ? v : (wpre + v) | (wpre & 0x80000000u);
+        sbase += S.wst[w];
+      }
+      tot = (v & 0x80000000u) ? v : (tot + v) | (tot & 0x80000000u);
+      n_slots += S.wst[w];
     }
-    if (wave == 0) {
-      uint32_t tot = 0;
-      for (int w = 0; w < kWaves; ++w) {
-        uint32_t v = S.wcnt[w];
-        tot = (v & 0x80000000u) ? v : (tot + v) | (tot & 0x80000000u);
-      }
-      if (lane == 0) {
-        unsigned long long agg = kFlagAgg | ((tot & 0x80000000u) ? kResetBit : 0ull) | (tot & 0x7FFFFFFFu);
-        st_state(&P.tileB[t], agg);
-      }
-      uint32_t prefix = (S.list[0].rel == 0) ? 0u : count_lookback(P, t);
-      if (lane == 0) {
-        S.prefix = prefix;
-        uint32_t incl = (tot & 0x80000000u) ? (tot & 0x7FFFFFFFu) : prefix + tot;
-        st_state(&P.tileB[t], kFlagFull | incl);
-      }
-    }
-    __syncthreads();
-    // exclusive count before this lane for the module open at its start
-    uint32_t lex = (excl & 0x80000000u) ? excl : (wpre + excl) | (wpre & 0x80000000u);
-    const uint32_t pre = (lex & 0x80000000u) ? (lex & 0x7FFFFFFFu) : S.prefix + lex;
-
-    // rank of a start at position p: starts of its module before it
-    auto rank_at = [&](int p) -> uint32_t {
+    if (tid == 0)
+      st_state(&P.tileB[t], kFlagAgg | ((tot & 0x80000000u) ? kResetBit : 0ull) | (tot & 0x7FFFFFFFu));
+    // starts of the module open at this lane's start, before it, inside this
+    // tile; for list entry 0 the tile prefix is added once it is known
+    const uint32_t lex = (excl & 0x80000000u) ? excl : (wpre + excl) | (wpre & 0x80000000u);
+    const uint32_t pre_local = lex & 0x7FFFFFFFu;
+    const bool lane_in_first = !(lex & 0x80000000u);  // module open at the lane start is list entry 0
+    auto rank_local = [&](int p) -> uint32_t {
       uint32_t below = starts & ((1u << p) - 1u);
       uint32_t rb = rst & ((2u << p) - 1u);
-      if (rb == 0) return pre + __popc(below);
+      if (rb == 0) return pre_local + __popc(below);
       int r = 31 - __builtin_clz(rb);
       return __popc(below & ~((1u << r) - 1u));
     };
+    // is the start at p in list entry 0 (ranks continue the tile prefix)?
+    auto in_first = [&](int p) -> bool { return lane_in_first && (rst & ((2u << p) - 1u)) == 0; };
 
-    // ---- module ends owned by this lane: positions 1..16 of the window
+    // ---- OpName strings (checked on the LDS copy; reported after the ranks
+    // are known)
+    uint32_t bad_names = 0;
     {
-      uint32_t ends = (L.bm >> 1) & 0xFFFFu;  // bit k <-> end at position k+1
-      while (ends) {
-        int k = __builtin_ctz(ends);
-        ends &= ends - 1;
-        int e = k + 1;
-        // module open just before position e
-        uint32_t rb = rst & ((1u << e) - 1u);  // module starts in [0, e)
-        uint32_t below = starts & ((e >= 32) ? ~0u : ((1u << e) - 1u));
-        uint32_t c;
-        int jm;
-        if (rb == 0) {
-          c = pre + __popc(below);
-          jm = L.j0;
-        } else {
-          int r = 31 - __builtin_clz(rb);
-          c = __popc(below & ~((1u << r) - 1u));
-          jm = lane_mod_at(L, r);
-        }
-        const LEnt& le = S.list[jm];
-        if (le.mod >= 0) P.mods[le.mod].n_total = c;
-      }
-    }
-
-    // ---- parse errors: chain nodes that are not valid instructions
-    {
-      uint32_t ee = errs;
-      while (ee) {
-        int p = __builtin_ctz(ee);
-        ee &= ee - 1;
-        int jm = lane_mod_at(L, p);
-        const LEnt& le = S.list[jm];
-        int64_t pos = L.a + p;
-        if (pos >= P.W || le.mod < 0) continue;
-        uint32_t code = start_code(P.words, S.tbl, pos, le.end);
-        if (code == 0) code = SPV_E_BAD_WORD_COUNT;  // not reachable: implausible implies a failing check
-        report_error(P.mods[le.mod], uint32_t(pos - le.off), code, rank_at(p));
-      }
-      // OpName strings
       uint32_t ns = starts & L.namemask;
       while (ns) {
         int p = __builtin_ctz(ns);
         ns &= ns - 1;
-        int64_t pos = L.a + p;
-        uint32_t wc = P.words[pos] >> 16;
-        if (!string_ok_short(P.words + pos + 2, int(wc) - 2)) {
-          int jm = lane_mod_at(L, p);
-          const LEnt& le = S.list[jm];
-          report_error(P.mods[le.mod], uint32_t(pos - le.off), SPV_E_BAD_STRING, rank_at(p));
+        int q = lrel + p;
+        uint32_t wc = S.tw[q] >> 16;
+        bool ok = true;
+        for (uint32_t k = 2; k + 1 < wc; ++k) {
+          uint32_t x = S.tw[q + k];
+          ok = ok && ((x - 0x01010101u) & ~x & 0x80808080u) == 0;
         }
-      }
-    }
-
-    // ---- instruction index: staged in LDS in tile order, then written with
-    // coalesced stores (a module's starts in a tile have consecutive ranks)
-    if (kIdx) {
-      const uint32_t nst = __popc(starts);
-      uint32_t sinc = nst;
-#pragma unroll
-      for (int d = 1; d < 64; d <<= 1) {
-        uint32_t u = __shfl_up(sinc, d);
-        if (lane >= d) sinc += u;
-      }
-      if (lane == 63) S.wst[wave] = sinc;
-      __syncthreads();
-      uint32_t sbase = sinc - nst, n_slots = 0;
-      for (int w = 0; w < kWaves; ++w) {
-        if (w < wave) sbase += S.wst[w];
-        n_slots += S.wst[w];
-      }
-      if (L.rst == 0) {
-        const int j0 = L.j0;
-        const uint32_t base_rank = (j0 == 0 ? S.prefix : 0u);
-#pragma unroll
-        for (int p = 0; p < kLaneWords; ++p) {
-          if ((starts >> p) & 1u) {
-            uint32_t below = __popc(starts & ((1u << p) - 1u));
-            uint32_t sl = sbase + below;
-            S.stage[sl] = uint32_t(tid * kLaneWords + p) | (L.w[p] << 16);
-            S.stagejm[sl] = uint8_t(j0);
-            if (pre + below == base_rank) S.slot0[j0] = sl;
-          }
-        }
-      } else {
-#pragma unroll
-        for (int p = 0; p < kLaneWords; ++p) {
-          if ((starts >> p) & 1u) {
-            uint32_t sl = sbase + __popc(starts & ((1u << p) - 1u));
-            int jm = lane_mod_at(L, p);
-            S.stage[sl] = uint32_t(tid * kLaneWords + p) | (L.w[p] << 16);
-            S.stagejm[sl] = uint8_t(jm);
-            if (rank_at(p) == (jm == 0 ? S.prefix : 0u)) S.slot0[jm] = sl;
-          }
-        }
-      }
-      __syncthreads();
-      for (uint32_t sl = tid; sl < n_slots; sl += kBlock) {
-        uint32_t v = S.stage[sl];
-        int jm = S.stagejm[sl];
-        const LEnt& le = S.list[jm];
-        if (le.info & kInfoHdrOk) {
-          int64_t dst = le.off + (jm == 0 ? S.prefix : 0u) + (sl - S.slot0[jm]);
-          P.idx_off[dst] = uint32_t(t0 + (v & 0xFFFFu) - le.off);
-          P.idx_op[dst] = uint16_t(v >> 16);
-        }
+        uint32_t x = S.tw[q + wc - 1];
+        uint32_t z = (x - 0x01010101u) & ~x & 0x80808080u;
+        ok = ok && z != 0 && (x >> (8 * (__builtin_ctz(z | 0x80000000u) >> 3))) == 0;
+        if (!ok) bad_names |= 1u << p;
       }
     }
 
@@ -1038,19 +1015,12 @@ __global__ __launch_bounds__(kBlock) void k_main(VParams P) {
 #pragma unroll
       for (int p = 0; p < kLaneWords; ++p) {
         if ((starts >> p) & 1u) {
-          uint32_t r = (L.nxr[p >> 1] >> (16 * (p & 1) + 8)) & 0xFFu;
+          uint32_t r = (L.rolep[p >> 2] >> (8 * (p & 3))) & 0xFFu;
           defm |= (r & 0xFu) << (p + 1);
           usem |= (r >> 4) << (p + 1);
         }
       }
       S.spill[tid] = ((defm >> 16) & 0xFu) | (((usem >> 16) & 0xFu) << 4);
-      __syncthreads();
-      if (tid > 0) {
-        uint32_t sp = S.spill[tid - 1];
-        defm |= sp & 0xFu;
-        usem |= (sp >> 4) & 0xFu;
-      }
-      uint32_t idm = (defm | usem) & 0xFFFFu;
       // LDS window for the result IDs of module jw in this tile: anchored at
       // the first result ID found by the lowest wave that has one
       const int jw = S.jw;
@@ -1066,6 +1036,12 @@ __global__ __launch_bounds__(kBlock) void k_main(VParams P) {
         if (lane == 0) S.wref[wave] = ref;
       }
       __syncthreads();
+      if (tid > 0) {
+        uint32_t sp = S.spill[tid - 1];
+        defm |= sp & 0xFu;
+        usem |= (sp >> 4) & 0xFu;
+      }
+      uint32_t idm = (defm | usem) & 0xFFFFu;
       uint32_t ref = 0xFFFFFFFFu;
       for (int w = kWaves - 1; w >= 0; --w)
         if (S.wref[w] != 0xFFFFFFFFu) ref = S.wref[w];
@@ -1074,7 +1050,7 @@ __global__ __launch_bounds__(kBlock) void k_main(VParams P) {
       // Hot loop: bound check and LDS-window insertion for lanes whose whole
       // segment belongs to one module; every other ID word (result outside
       // the window, hash-mode module, lanes with a module start) is collected
-      // in `rare` and handled below from memory.
+      // in `rare` and handled below.
       uint32_t rare = 0;
       if (L.rst == 0) {
         const int j0 = L.j0;
@@ -1114,7 +1090,7 @@ __global__ __launch_bounds__(kBlock) void k_main(VParams P) {
         int jm = lane_mod_at(L, p);
         const LEnt& le = S.list[jm];
         if (!(le.info & kInfoHdrOk)) continue;
-        uint32_t v = P.words[L.a + p];
+        uint32_t v = S.tw[lrel + p];
         bool is_def = (defm >> p) & 1u;
         if (win_on && is_def && jm == jw && v != 0u && v < le.bound && v >= base64 &&
             v - base64 < 64u * kWinWords) {
@@ -1132,33 +1108,119 @@ __global__ __launch_bounds__(kBlock) void k_main(VParams P) {
         for (int k = 0; k < 4; ++k) {
           bool d = (sp >> k) & 1u, u = (sp >> (4 + k)) & 1u;
           if (!(d || u)) continue;
-          int64_t pos = L.a + 16 + k;
           int jm = lane_mod_at(L, 15);
           const LEnt& le = S.list[jm];
-          if (le.info & kInfoHdrOk) id_check(P, le, P.words[pos], d, &S.modflags[jm], &S.moddef[jm]);
+          if (le.info & kInfoHdrOk) id_check(P, le, S.tw[kTileWords + k], d, &S.modflags[jm], &S.moddef[jm]);
         }
       }
       __syncthreads();
-      // flush the window: one device atomic per 64 result IDs
+      // window flush: one device atomic per 64 result IDs; the returned words
+      // are examined at the start of the next tile
+      fl_mod = win_on ? int64_t(S.list[jw].mod) : -1;
       if (win_on && tid < kWinWords) {
-        unsigned long long b = S.win[tid];
-        if (b) {
-          const LEnt& le = S.list[jw];
-          unsigned long long old = atomicOr(&P.idmap[le.off + (base64 >> 6) + tid], b);
-          if (old & b) atomicOr(&S.modflags[jw], kModDup);
-          atomicAdd(&S.moddef[jw], uint32_t(__popcll(b & ~old)));
-        }
+        fl_bits = S.win[tid];
+        fl_old = fl_bits ? atomicOr(&P.idmap[S.list[jw].off + (base64 >> 6) + tid], fl_bits) : 0ull;
       }
-      __syncthreads();
       if (tid < S.K && S.list[tid].mod >= 0) {
         ModState& ms = P.mods[S.list[tid].mod];
         if (S.modflags[tid]) atomicOr(&ms.flags, S.modflags[tid]);
         if (S.moddef[tid]) atomicAdd(&ms.def_count, S.moddef[tid]);
       }
     }
-    } while (false);
-    if (go_serial) serial_tile<kSem, kIdx>(S, P, t, t0, t1, serialE);
+
+    // ---- index entries staged in LDS in tile order (slot = plain scan)
+    if (kIdx) {
+#pragma unroll
+      for (int p = 0; p < kLaneWords; ++p) {
+        if ((starts >> p) & 1u) {
+          uint32_t sl = sbase + __popc(starts & ((1u << p) - 1u));
+          S.stage[sl] = uint32_t(lrel + p) | (L.w[p] << 16);
+          if (rank_local(p) == 0u) S.slot0[L.rst ? lane_mod_at(L, p) : L.j0] = sl;
+        }
+      }
+    }
+
+    // ---- tile prefix of list entry 0 (count look-back), inclusive state
+    if (wave == 0) {
+      uint32_t prefix = (S.list[0].rel == 0) ? 0u : count_lookback(P, t);
+      if (lane == 0) {
+        S.prefix = prefix;
+        uint32_t incl = (tot & 0x80000000u) ? (tot & 0x7FFFFFFFu) : prefix + tot;
+        st_state(&P.tileB[t], kFlagFull | incl);
+      }
+    }
     __syncthreads();
+    const uint32_t prefix = S.prefix;
+    // claim the next tile now: the atomic's latency hides behind the rest of
+    // this tile, and the claimed tile starts right after
+    if (tid == 0) S.tnext = atomicAdd(&P.ctrl[kCtlClaim], 1u);
+
+    // ---- instruction index: coalesced stores of the staged entries
+    if (kIdx) {
+      const int K = S.K;
+      for (uint32_t sl = tid; sl < n_slots; sl += kBlock) {
+        // modules with starts in this tile own consecutive slot ranges in
+        // list order; modules without starts keep slot0 = 0xFFFFFFFF
+        int jm = 0;
+        for (int j = 1; j < K; ++j)
+          if (S.slot0[j] <= sl) jm = j;
+        const LEnt& le = S.list[jm];
+        if (le.info & kInfoHdrOk) {
+          uint32_t v = S.stage[sl];
+          int64_t dst = le.off + (jm == 0 ? prefix : 0u) + (sl - S.slot0[jm]);
+          P.idx_off[dst] = uint32_t(t0 + (v & 0xFFFFu) - le.off);
+          P.idx_op[dst] = uint16_t(v >> 16);
+        }
+      }
+    }
+
+    // ---- module ends owned by this lane: positions 1..16 of the window
+    {
+      uint32_t ends = (L.bm >> 1) & 0xFFFFu;  // bit k <-> end at position k+1
+      while (ends) {
+        int k = __builtin_ctz(ends);
+        ends &= ends - 1;
+        int e = k + 1;
+        // module open just before position e
+        uint32_t rb = rst & ((1u << e) - 1u);  // module starts in [0, e)
+        uint32_t below = starts & ((1u << e) - 1u);
+        uint32_t c;
+        int jm;
+        if (rb == 0) {
+          c = pre_local + __popc(below) + (lane_in_first ? prefix : 0u);
+          jm = L.j0;
+        } else {
+          int r = 31 - __builtin_clz(rb);
+          c = __popc(below & ~((1u << r) - 1u));
+          jm = lane_mod_at(L, r);
+        }
+        const LEnt& le = S.list[jm];
+        if (le.mod >= 0) P.mods[le.mod].n_total = c;
+      }
+    }
+
+    // ---- parse errors: chain nodes that are not valid instructions, and
+    // OpName starts whose string is malformed
+    {
+      uint32_t ee = errs | bad_names;
+      while (ee) {
+        int p = __builtin_ctz(ee);
+        ee &= ee - 1;
+        int jm = lane_mod_at(L, p);
+        const LEnt& le = S.list[jm];
+        int64_t pos = L.a + p;
+        if (pos >= P.W || le.mod < 0) continue;
+        uint32_t code = ((bad_names >> p) & 1u) ? uint32_t(SPV_E_BAD_STRING) : start_code(P.words, S.tbl, pos, le.end);
+        if (code == 0) code = SPV_E_BAD_WORD_COUNT;  // not reachable: implausible implies a failing check
+        uint32_t rank = rank_local(p) + (in_first(p) ? prefix : 0u);
+        report_error(P.mods[le.mod], uint32_t(pos - le.off), code, rank);
+      }
+    }
+    } while (false);
+    if (go_serial) {
+      if (tid == 0) S.tnext = atomicAdd(&P.ctrl[kCtlClaim], 1u);
+      serial_tile<kSem, kIdx>(S, P, t, t0, t1, serialE);
+    }
   }
 }
 
@@ -1210,6 +1272,7 @@ __global__ __launch_bounds__(256) void k_finalize(VParams P, int phase) {
 __global__ __launch_bounds__(kBlock) void k_pass2(VParams P) {
   __shared__ Shared S;
   if (P.ctrl[kCtlPass2] == 0) return;
+  if (threadIdx.x == 0) S.cache_ok = 0;
   init_table(S.tbl);
   const int tid = threadIdx.x;
   const int wave = tid >> 6;
@@ -1318,7 +1381,7 @@ __global__ __launch_bounds__(kBlock) void k_pass2(VParams P) {
         }
         uint32_t ent = __shfl_up(ex, 1);
         if (lane == 0) ent = Ew;
-        const uint64_t reach = lane_forward(L, ent == kDead ? 99u : ent);
+        const uint32_t reach = lane_forward(L, ent == kDead ? 99u : ent);
         const uint32_t starts = uint32_t(reach) & L.plmask & ~L.farmask & ~L.hdr & 0xFFFFu;
         const bool far_hit = (uint32_t(reach) & L.farmask & 0xFFFFu) != 0 || ent == kFar;
         amb = __syncthreads_or(far_hit);
@@ -1326,7 +1389,7 @@ __global__ __launch_bounds__(kBlock) void k_pass2(VParams P) {
           uint32_t usem = 0;
 #pragma unroll
           for (int p = 0; p < kLaneWords; ++p)
-            if ((starts >> p) & 1u) usem |= ((L.nxr[p >> 1] >> (16 * (p & 1) + 12)) & 0xFu) << (p + 1);
+            if ((starts >> p) & 1u) usem |= ((L.rolep[p >> 2] >> (8 * (p & 3) + 4)) & 0xFu) << (p + 1);
           S.spill[tid] = (usem >> 16) & 0xFu;
           __syncthreads();
           if (tid > 0) usem |= S.spill[tid - 1];

@@ -1,0 +1,117 @@
+"""The library's calls are stream-ordered, allocation-free and host-sync-free,
+so they can be captured in a HIP graph: capture spv_validate once, replay it
+several times on new inputs of the same shape (with eager work and
+synchronisations between replays) and check every replay against the eager
+result and the oracle.  Also: parity does not depend on the persistent grid
+size."""
+import numpy as np
+import pytest
+
+import oracle
+import spvgen
+from gpu_util import compare
+
+pytestmark = pytest.mark.gpu
+
+
+_BASE = None
+
+
+def _batch(seed):
+    """The same 24 modules for every seed (same sizes); each seed injects
+    faults (which keep the word count) into a different subset."""
+    global _BASE
+    if _BASE is None:
+        _BASE = [spvgen.gen_module([40, i], 3000) for i in range(24)]
+    rng = np.random.default_rng(seed)
+    mods = []
+    for i, m in enumerate(_BASE):
+        if seed and i % 5 == seed % 5:
+            m = spvgen.FAULTS[(i + seed) % 3](m, rng)
+        mods.append(m)
+    return spvgen.pack(mods)
+
+
+def test_graph_capture_replays_match_eager():
+    import torch
+
+    import paper_2305_09493_amd as spv
+    b0 = _batch(0)
+    W, M = b0.words.size, b0.n_modules
+    words = torch.zeros(W, dtype=torch.int32, device="cuda")
+    mod_off = torch.from_numpy(b0.mod_off).cuda()
+    res = torch.empty((M, 4), dtype=torch.int32, device="cuda")
+    io = torch.empty(W, dtype=torch.int32, device="cuda")
+    iop = torch.empty(W, dtype=torch.int16, device="cuda")
+    ctx = spv.context()
+    ws = torch.empty(ctx.workspace_size(M, W), dtype=torch.uint8, device="cuda")
+    words.copy_(torch.from_numpy(b0.words.view(np.int32)))
+    spv.validate(words, mod_off, out=(res, io, iop), workspace=ws)  # warm-up outside capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            spv.validate(words, mod_off, out=(res, io, iop), workspace=ws, stream=s)
+    torch.cuda.synchronize()
+    for seed in range(1, 5):
+        b = _batch(seed)
+        assert b.words.size == W and np.array_equal(b.mod_off, b0.mod_off)
+        words.copy_(torch.from_numpy(b.words.view(np.int32)))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        got = res.cpu().numpy().view(np.uint32).copy()
+        # eager on the same input, then the oracle
+        r2, _, _ = spv.validate(words, mod_off)
+        torch.cuda.synchronize()
+        o = oracle.validate(b.words, b.mod_off, index=False)
+        exp = np.stack([o[k] for k in ("code", "sem_mask", "err_word", "n_inst")], axis=1)
+        assert np.array_equal(got, r2.cpu().numpy().view(np.uint32)), seed
+        assert np.array_equal(got, exp), seed
+        _ = torch.ones(1 << 20, device="cuda").sum().item()  # unrelated eager work between replays
+
+
+@pytest.mark.parametrize("bpc", [1, 2, 8])
+def test_parity_independent_of_grid(bpc):
+    import paper_2305_09493_amd as spv
+    ctx = spv.context()
+    old = ctx.get_tuning()[0]
+    try:
+        ctx.set_tuning(blocks_per_cu=bpc)
+        b = spvgen.config3(n_modules=96, n_faults=9, median=1200.0, hi=40_000)
+        compare(b.words, b.mod_off, label=f"blocks_per_cu={bpc}")
+        m = spvgen.gen_module(77, 120_000)
+        compare(m.words, [0, m.words.size], label=f"one module, blocks_per_cu={bpc}")
+    finally:
+        ctx.set_tuning(blocks_per_cu=old)
+
+
+def test_autotuner_picks_a_candidate_and_keeps_parity(tmp_path, monkeypatch):
+    import torch
+
+    import paper_2305_09493_amd as spv
+    from paper_2305_09493_amd import tune
+    monkeypatch.setenv("SPVGPU_TUNE_CACHE", str(tmp_path / "tune.json"))
+    ctx = spv.context()
+    old = ctx.get_tuning()
+    try:
+        b = spvgen.config3(n_modules=64, n_faults=6, median=1500.0, hi=30_000)
+        w = torch.from_numpy(b.words.view(np.int32)).cuda()
+        mo = torch.from_numpy(b.mod_off).cuda()
+        r = tune.autotune_validate(w, mo, candidates=(1, 2, 4))
+        assert r["blocks_per_cu"] in (1, 2, 4)
+        ctx.set_tuning(blocks_per_cu=old[0])
+        assert tune.apply("validate", b.words.size)["blocks_per_cu"] == r["blocks_per_cu"]
+        compare(b.words, b.mod_off, label="after autotune")
+        recs = spvgen.pack_records([spvgen.gen_module([41, i], 2000) for i in range(4)])
+        d = dict(op=torch.from_numpy(recs["op"].view(np.int16)).cuda(),
+                 opnd_off=torch.from_numpy(recs["opnd_off"]).cuda(),
+                 opnd=torch.from_numpy(recs["opnd"].view(np.int32)).cuda(),
+                 str_off=torch.from_numpy(recs["str_off"]).cuda(),
+                 chars=torch.from_numpy(recs["chars"]).cuda(),
+                 rec_mod_off=torch.from_numpy(recs["rec_mod_off"]).cuda())
+        e = tune.autotune_encode(d, candidates=(256, 1024))
+        assert e["encode_block"] in (256, 1024)
+    finally:
+        ctx.set_tuning(blocks_per_cu=old[0], encode_block=old[1])
