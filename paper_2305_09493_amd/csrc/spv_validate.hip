@@ -754,7 +754,7 @@ __global__ __launch_bounds__(256) void k_plan(VParams P, int64_t chunk) {
 // main pass: boundary recovery, parse checks, instruction index, result-ID
 // checks.
 template <bool kSem, bool kIdx>
-__global__ __launch_bounds__(kBlock) void k_main(VParams P) {
+__global__ __launch_bounds__(kBlock, 4) void k_main(VParams P) {
   __shared__ Shared S;
   if (threadIdx.x == 0) S.cache_ok = 0;
   init_table(S.tbl);
@@ -768,6 +768,9 @@ __global__ __launch_bounds__(kBlock) void k_main(VParams P) {
   // returned words are examined at the start of the next tile
   unsigned long long fl_old = 0, fl_bits = 0;
   int64_t fl_mod = -1;
+  // words of the next tile, loaded during the tail of the current one
+  uint4 pf[kLaneWords / 4];
+  long long pf_tile = -1;
 
   for (;;) {
     __syncthreads();
@@ -800,9 +803,10 @@ __global__ __launch_bounds__(kBlock) void k_main(VParams P) {
     // in LDS (strings and rare paths read the LDS copy)
     if (L.a + kLaneWords <= P.W) {
       const uint4* src = reinterpret_cast<const uint4*>(P.words + L.a);
+      const bool have = pf_tile == t;
 #pragma unroll
       for (int i = 0; i < kLaneWords / 4; ++i) {
-        uint4 v = src[i];
+        uint4 v = have ? pf[i] : src[i];
         L.w[4 * i] = v.x;
         L.w[4 * i + 1] = v.y;
         L.w[4 * i + 2] = v.z;
@@ -995,16 +999,21 @@ __global__ __launch_bounds__(kBlock) void k_main(VParams P) {
       while (ns) {
         int p = __builtin_ctz(ns);
         ns &= ns - 1;
-        int q = lrel + p;
-        uint32_t wc = S.tw[q] >> 16;
+        const int q = lrel + p;
+        const uint32_t nw = (S.tw[q] >> 16) - 2;  // string words: 1..12 on this path
+        uint32_t x[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) x[k] = (uint32_t(k) < nw) ? S.tw[q + 2 + k] : 0u;
         bool ok = true;
-        for (uint32_t k = 2; k + 1 < wc; ++k) {
-          uint32_t x = S.tw[q + k];
-          ok = ok && ((x - 0x01010101u) & ~x & 0x80808080u) == 0;
+        uint32_t last = 0;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+          uint32_t z = (x[k] - 0x01010101u) & ~x[k] & 0x80808080u;
+          if (uint32_t(k) + 1 < nw) ok = ok && z == 0;
+          if (uint32_t(k) + 1 == nw) last = x[k];
         }
-        uint32_t x = S.tw[q + wc - 1];
-        uint32_t z = (x - 0x01010101u) & ~x & 0x80808080u;
-        ok = ok && z != 0 && (x >> (8 * (__builtin_ctz(z | 0x80000000u) >> 3))) == 0;
+        uint32_t z = (last - 0x01010101u) & ~last & 0x80808080u;
+        ok = ok && z != 0 && (last >> (8 * (__builtin_ctz(z | 0x80000000u) >> 3))) == 0;
         if (!ok) bad_names |= 1u << p;
       }
     }
@@ -1132,28 +1141,51 @@ __global__ __launch_bounds__(kBlock) void k_main(VParams P) {
     if (kIdx) {
 #pragma unroll
       for (int p = 0; p < kLaneWords; ++p) {
-        if ((starts >> p) & 1u) {
-          uint32_t sl = sbase + __popc(starts & ((1u << p) - 1u));
-          S.stage[sl] = uint32_t(lrel + p) | (L.w[p] << 16);
-          if (rank_local(p) == 0u) S.slot0[L.rst ? lane_mod_at(L, p) : L.j0] = sl;
+        if ((starts >> p) & 1u) S.stage[sbase + __popc(starts & ((1u << p) - 1u))] = uint32_t(lrel + p) | (L.w[p] << 16);
+      }
+      // first slot of each module in this tile: the first start of the module
+      // open at this lane's start when no earlier lane had one, and the first
+      // start after each module start inside the lane
+      if (starts) {
+        const uint32_t first_rst = rst ? uint32_t(__builtin_ctz(rst)) : 32u;
+        if (pre_local == 0 && (starts & ((first_rst >= 32u) ? ~0u : ((1u << first_rst) - 1u))))
+          S.slot0[L.j0] = sbase;
+        uint32_t rr = rst;
+        while (rr) {
+          const int r = __builtin_ctz(rr);
+          rr &= rr - 1;
+          const uint32_t upto = rr ? ((1u << __builtin_ctz(rr)) - 1u) : 0xFFFFu;
+          if (starts & upto & ~((2u << r) - 1u)) S.slot0[lane_mod_at(L, r)] = sbase + __popc(starts & ((1u << r) - 1u));
         }
       }
     }
 
-    // ---- tile prefix of list entry 0 (count look-back), inclusive state
+    // ---- tile prefix of list entry 0 (count look-back), inclusive state;
+    // the next tile is claimed now (its latency hides behind the look-back)
+    // so that its words can be loaded during the rest of this tile
     if (wave == 0) {
+      uint32_t tn = 0;
+      if (lane == 0) tn = atomicAdd(&P.ctrl[kCtlClaim], 1u);
       uint32_t prefix = (S.list[0].rel == 0) ? 0u : count_lookback(P, t);
       if (lane == 0) {
         S.prefix = prefix;
+        S.tnext = tn;
         uint32_t incl = (tot & 0x80000000u) ? (tot & 0x7FFFFFFFu) : prefix + tot;
         st_state(&P.tileB[t], kFlagFull | incl);
       }
     }
     __syncthreads();
     const uint32_t prefix = S.prefix;
-    // claim the next tile now: the atomic's latency hides behind the rest of
-    // this tile, and the claimed tile starts right after
-    if (tid == 0) S.tnext = atomicAdd(&P.ctrl[kCtlClaim], 1u);
+    {
+      const long long tn = S.tnext;
+      const int64_t an = tn * kTileWords + int64_t(tid) * kLaneWords;
+      if (tn < P.n_tiles && an + kLaneWords <= P.W) {
+        const uint4* src = reinterpret_cast<const uint4*>(P.words + an);
+#pragma unroll
+        for (int i = 0; i < kLaneWords / 4; ++i) pf[i] = src[i];
+        pf_tile = tn;
+      }
+    }
 
     // ---- instruction index: coalesced stores of the staged entries
     if (kIdx) {
