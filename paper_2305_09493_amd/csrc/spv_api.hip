@@ -13,6 +13,8 @@ struct spv_ctx {
   int device;
   int n_cu;
   int blocks_per_cu;   // persistent grid of the decode/validate kernels
+  int occupancy;       // resident blocks per CU of the main kernel
+  int chain_occ;       // resident blocks per CU of the chain pass
   int encode_block;    // records per encode block
   hipError_t last;
   char msg[256];
@@ -23,6 +25,7 @@ struct spv_ctx {
 
 namespace spv {
 int main_occupancy();
+int chain_occupancy();
 }
 
 namespace {
@@ -89,8 +92,13 @@ int run_validate(spv_ctx* ctx, const uint32_t* words, const int64_t* mod_off, in
   p.tfm = reinterpret_cast<int32_t*>(base + L.tfm);
   p.mods = reinterpret_cast<spv::ModState*>(base + L.mods);
   p.idmap = reinterpret_cast<unsigned long long*>(base + L.idmap);
+  p.tsum = reinterpret_cast<uint32_t*>(base + L.tsum);
+  p.lst = reinterpret_cast<uint32_t*>(base + L.lst);
+  p.tres = reinterpret_cast<uint32_t*>(base + L.tres);
+  p.rstate = reinterpret_cast<unsigned long long*>(base + L.rstate);
   p.semantic = semantic;
   p.index = index ? 1 : 0;
+  p.sched_static = 0;
   hipStream_t s = static_cast<hipStream_t>(stream);
 
   int64_t plan_units = n_modules > p.n_tiles ? n_modules : p.n_tiles;
@@ -117,7 +125,26 @@ int run_validate(spv_ctx* ctx, const uint32_t* words, const int64_t* mod_off, in
       hipError_t he = hipEventRecord(ev->first, s);
       if (he != hipSuccess) return fail_hip(ctx, he);
     }
-    spv::launch_main(p, int(grid), s);
+    // chain pass and resolve pass: entries and count prefixes of all tiles
+    int64_t cgrid = int64_t(ctx->n_cu) * ctx->chain_occ;
+    if (cgrid > p.n_tiles) cgrid = p.n_tiles;
+    spv::launch_chain(p, int(cgrid), s);
+    if ((r = check_launch(ctx))) return r;
+    spv::launch_resolve(p, s);
+    if ((r = check_launch(ctx))) return r;
+    // Static tile order needs every block resident at once: a cooperative
+    // launch guarantees that.  Stream capture keeps the claimed order.
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    hipError_t he = hipStreamIsCapturing(s, &cs);
+    if (he != hipSuccess) return fail_hip(ctx, he);
+    p.sched_static = (cs == hipStreamCaptureStatusNone && ctx->blocks_per_cu <= ctx->occupancy) ? 1 : 0;
+    he = spv::launch_main(p, int(grid), s);
+    if (he != hipSuccess && p.sched_static) {
+      (void)hipGetLastError();
+      p.sched_static = 0;
+      he = spv::launch_main(p, int(grid), s);
+    }
+    if (he != hipSuccess) return fail_hip(ctx, he);
     if ((r = check_launch(ctx))) return r;
     if (ev) {
       hipError_t he = hipEventRecord(ev->second, s);
@@ -155,6 +182,9 @@ int spv_create(spv_ctx** out, int hip_device) {
   {
     DeviceGuard g(hip_device);
     int occ = spv::main_occupancy();
+    c->occupancy = occ;
+    int cocc = spv::chain_occupancy();
+    c->chain_occ = cocc > 0 ? cocc : 2;
     c->blocks_per_cu = occ > 0 ? (occ < 8 ? occ : 8) : 2;
   }
   c->encode_block = 1024;

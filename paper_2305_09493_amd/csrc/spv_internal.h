@@ -15,9 +15,12 @@ namespace spv {
 
 // ---- tiling --------------------------------------------------------------
 constexpr int kLaneWords = 16;                    // words owned by one lane
-constexpr int kWaves = 4;                         // waves per tile block
-constexpr int kBlock = 64 * kWaves;               // 256 threads
-constexpr int kTileWords = kLaneWords * kBlock;   // 4096 words per tile
+#ifndef SPV_TILE_WAVES
+#define SPV_TILE_WAVES 4
+#endif
+constexpr int kWaves = SPV_TILE_WAVES;            // waves per tile block
+constexpr int kBlock = 64 * kWaves;               // threads per tile block
+constexpr int kTileWords = kLaneWords * kBlock;   // words per tile
 constexpr int kListMax = 64;                      // module starts per tile window (fast path)
 constexpr int kMaxSpanTiles = 17;                 // a 65535-word instruction spans <= 17 tiles
 
@@ -70,10 +73,18 @@ static_assert(sizeof(ModState) == 48, "ModState layout");
 
 // ---- workspace layout ----------------------------------------------------
 struct Layout {
-  size_t ctrl, tileA, tileB, tfm, mods, idmap, total;
+  size_t ctrl, tileA, tileB, tfm, mods, idmap, tsum, lst, tres, rstate, total;
 };
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// tiles per block of the resolve pass
+constexpr int kResolveTiles = 256;
+
+// Tile states are polled and written by many blocks with device-scope
+// operations, which the memory system serializes per 128-byte line: each
+// tile's state gets a line of its own (stride in 64-bit words).
+constexpr int kStateStride = 16;
 
 inline Layout make_layout(int64_t n_modules, int64_t n_words) {
   Layout L;
@@ -82,21 +93,39 @@ inline Layout make_layout(int64_t n_modules, int64_t n_words) {
   L.ctrl = off;
   off = align256(off + 256);
   L.tileA = off;
-  off = align256(off + 8 * size_t(n_tiles + 1));
+  off = align256(off + 8 * kStateStride * size_t(n_tiles + 1));
   L.tileB = off;
-  off = align256(off + 8 * size_t(n_tiles + 1));
+  off = align256(off + 8 * kStateStride * size_t(n_tiles + 1));
   L.tfm = off;
   off = align256(off + 4 * size_t(n_tiles + 1));
   L.mods = off;
   off = align256(off + sizeof(ModState) * size_t(n_modules + 1));
   L.idmap = off;
   off = align256(off + 8 * size_t(n_words + 1));
+  L.tsum = off;
+  off = align256(off + 16 * size_t(n_tiles + 1));
+  L.lst = off;
+  off = align256(off + 4 * size_t(kBlock) * size_t(n_tiles + 1));
+  L.tres = off;
+  off = align256(off + 8 * size_t(n_tiles + 1));
+  L.rstate = off;
+  off = align256(off + 8 * kStateStride * size_t(n_tiles / kResolveTiles + 2));
   L.total = off;
   return L;
 }
 
 // control words (uint32) at the start of the workspace
-enum { kCtlClaim = 0, kCtlClaim2 = 1, kCtlPass2 = 2, kCtlSpinErr = 3 };
+enum { kCtlClaim = 0, kCtlClaim2 = 1, kCtlPass2 = 2, kCtlSpinErr = 3, kCtlMode = 4, kCtlClaimR = 5, kCtlDoneR = 6 };
+// kCtlMode: kModeResolved when the chain and resolve passes settled every
+// tile's entry and count prefix (the main pass then walks without look-back);
+// anything else selects the single-pass walk with look-back.
+constexpr uint32_t kModeResolved = 1u;
+// per-tile summary of the chain pass (4 words): word 0 = exit offset (bits
+// 0..7) | flags, word 1 = candidate chain of lane 0 before its first module
+// start, word 2 = starts of the module open at the tile start (lane 0's
+// entry-dependent ones excluded), word 3 = starts after the tile's last
+// module start
+constexpr uint32_t kSumFallback = 1u << 31, kSumModStart = 1u << 30, kSumReset = 1u << 29;
 
 // Every wait on another tile's published state gives up after this many
 // polls (seconds of waiting) and flags kCtlSpinErr instead of hanging; the
@@ -117,8 +146,16 @@ struct VParams {
   int32_t* tfm;
   ModState* mods;
   unsigned long long* idmap;
+  uint32_t* tsum;   // chain-pass tile summaries (4 words per tile)
+  uint32_t* lst;    // chain-pass lane records: starts | parse-error nodes << 16
+  uint32_t* tres;   // resolved tile entry and count prefix (2 words per tile)
+  unsigned long long* rstate;  // resolve-pass block states (look-back)
   int semantic;
   int index;
+  // 1: tile t is processed by block t mod gridDim.x (the grid is launched
+  // cooperatively, so every block is resident); 0: tiles are claimed in
+  // order from a counter
+  int sched_static;
 };
 
 // Grammar entry for opcode < 256 (index 256 = any other opcode):
@@ -134,7 +171,9 @@ constexpr int kOpName = 5;
 struct Params;  // forward
 
 void launch_plan(const VParams& p, int grid, hipStream_t s);
-void launch_main(const VParams& p, int grid, hipStream_t s);
+hipError_t launch_main(const VParams& p, int grid, hipStream_t s);
+void launch_chain(const VParams& p, int grid, hipStream_t s);
+void launch_resolve(const VParams& p, hipStream_t s);
 void launch_finalize(const VParams& p, int phase, hipStream_t s);
 void launch_pass2(const VParams& p, int grid, hipStream_t s);
 

@@ -66,19 +66,25 @@ __device__ __constant__ GEnt kGrammar[12] = {
     {253, 1, 1, 0x0, 0x0},     // OpReturn
 };
 
+// LDS grammar entry of an opcode (0 = unknown): bits 0..6 smallest word
+// count, bit 7 string operand, bits 8..23 count of accepted word counts,
+// bits 24..27 result-ID slots, bits 28..31 ID-use slots.
+constexpr uint32_t kEntStr = 0x80u;
+
 __device__ __forceinline__ void init_table(uint32_t* tbl) {
   for (int i = threadIdx.x; i < 257; i += blockDim.x) tbl[i] = 0;
   __syncthreads();
   if (threadIdx.x < 12) {
     GEnt g = kGrammar[threadIdx.x];
-    tbl[g.op] = uint32_t(g.lo) | (uint32_t(g.nok) << 8) | (uint32_t(g.def) << 24) | (uint32_t(g.use) << 28);
+    tbl[g.op] = uint32_t(g.lo) | (g.op == kOpName ? kEntStr : 0u) | (uint32_t(g.nok) << 8) | (uint32_t(g.def) << 24) |
+                (uint32_t(g.use) << 28);
   }
   __syncthreads();
 }
 
 __device__ __forceinline__ uint32_t tbl_lookup(const uint32_t* tbl, uint32_t op) { return tbl[op < 256u ? op : 256u]; }
 __device__ __forceinline__ bool tbl_plausible(uint32_t e, uint32_t wc) {
-  return (wc - (e & 0xFFu)) < ((e >> 8) & 0xFFFFu);
+  return (wc - (e & 0x7Fu)) < ((e >> 8) & 0xFFFFu);
 }
 
 // Tile states carry their whole message in one 64-bit word, so relaxed
@@ -203,12 +209,15 @@ struct Shared {
   uint32_t moddef[kListMax];
   uint32_t slot0[kListMax];    // first staging slot of each module's starts in this tile
   unsigned long long win[kWinWords];  // result-ID window bitmap of module jw
+  uint32_t nname;              // OpName starts compacted into stage[] for the string checks
+  uint32_t badb[kTileWords / 32];  // tile positions whose OpName string is malformed
   LEnt cache;                  // module containing the previous tile's start
   int cache_ok;
 };
 
 // Build the list of non-empty modules overlapping [t0, t1 + 16] (wave 0).
-__device__ __forceinline__ void build_list(Shared& S, const VParams& P, long long t, int64_t t0, int64_t t1) {
+template <class SH>
+__device__ __forceinline__ void build_list(SH& S, const VParams& P, long long t, int64_t t0, int64_t t1) {
   const int lane = lane_id();
   // a block's previous tile may have lain in a module that also covers this
   // whole tile window: then that module is the only list entry
@@ -291,7 +300,8 @@ __device__ __forceinline__ void build_list(Shared& S, const VParams& P, long lon
   }
 }
 
-__device__ __forceinline__ int list_find(const Shared& S, int32_t rel) {
+template <class SH>
+__device__ __forceinline__ int list_find(const SH& S, int32_t rel) {
   // largest j with list[j].rel <= rel (list[0].rel <= 0 <= rel)
   int lo = 0, hi = S.K - 1;
   while (lo < hi) {
@@ -309,34 +319,41 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
 }
 
 // Count look-back (called by a whole wave): instruction starts of the module
-// open at tile t's start that lie before it.  The wave reads 64 predecessor
-// states per round trip and stops at the nearest inclusive state or the
-// nearest aggregate of a tile in which a module starts.
-__device__ __forceinline__ uint32_t count_lookback(const VParams& P, long long t) {
+// open at tile t's start that lie before it.  The wave reads 256 predecessor
+// states per round trip (4 per lane, nearest first) and stops at the nearest
+// inclusive state or the nearest aggregate of a tile in which a module
+// starts.
+__device__ __forceinline__ uint32_t count_lookback(const VParams& P, const unsigned long long* states, long long t) {
   const int lane = lane_id();
   uint32_t prefix = 0;
   long long hi = t - 1;
   uint32_t spins = 0;
   while (hi >= 0) {
-    long long u = hi - lane;
-    unsigned long long st = (u >= 0) ? ld_state(&P.tileB[u]) : kFlagFull;
-    uint64_t f = st & kFlagMask;
-    bool stop = f == kFlagFull || (f == kFlagAgg && (st & kResetBit));
-    uint64_t stopm = __ballot(stop);
-    uint64_t unpub = __ballot(f == 0);
-    int sl = stopm ? int(__builtin_ctzll(stopm)) : 64;
-    uint64_t need = (sl >= 63) ? ~0ull : ((2ull << sl) - 1ull);
-    if (unpub & need) {
-      if (++spins > kSpinLimit) {
-        if (lane == 0) atomicOr(&P.ctrl[kCtlSpinErr], 1u);
-        break;
-      }
-      __builtin_amdgcn_s_sleep(1);
-      continue;
+    unsigned long long st[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const long long u = hi - lane - 64 * k;
+      st[k] = (u >= 0) ? ld_state(&states[u * kStateStride]) : kFlagFull;
     }
-    prefix += wave_sum_u32(lane <= sl ? uint32_t(st) : 0u);
-    if (sl < 64) break;
-    hi -= 64;
+    int k = 0;
+    for (; k < 4; ++k) {
+      const uint64_t f = st[k] & kFlagMask;
+      const bool stop = f == kFlagFull || (f == kFlagAgg && (st[k] & kResetBit));
+      const uint64_t stopm = __ballot(stop);
+      const uint64_t unpub = __ballot(f == 0);
+      const int sl = stopm ? int(__builtin_ctzll(stopm)) : 64;
+      const uint64_t need = (sl >= 63) ? ~0ull : ((2ull << sl) - 1ull);
+      if (unpub & need) break;
+      prefix += wave_sum_u32(lane <= sl ? uint32_t(st[k]) : 0u);
+      if (sl < 64) return prefix;
+      hi -= 64;
+    }
+    if (k == 4) continue;
+    if (++spins > kSpinLimit) {
+      if (lane == 0) atomicOr(&P.ctrl[kCtlSpinErr], 1u);
+      break;
+    }
+    __builtin_amdgcn_s_sleep(1);
   }
   return prefix;
 }
@@ -353,7 +370,7 @@ __device__ __forceinline__ uint32_t entry_lookback(const VParams& P, long long t
     }
     long long u = t - 1 - lane;
     bool real = lane < kMaxSpanTiles && u >= 0;
-    unsigned long long st = real ? ld_state(&P.tileA[u]) : kFlagAgg;
+    unsigned long long st = real ? ld_state(&P.tileA[(u) * kStateStride]) : kFlagAgg;
     unsigned long long st0 = __shfl(st, 0);
     if ((st0 & kFlagMask) == kFlagFull) return uint32_t(st0);
     bool pub = (st & kFlagMask) != 0;
@@ -388,13 +405,16 @@ struct Lane {
   uint32_t namemask; // OpName candidate starts
   uint32_t rolep[kLaneWords / 4];  // role bits per position (8 bits: result slots | use slots << 4)
   uint64_t F;        // transfer function
+  uint32_t reach0;   // fast lanes: chain from the first candidate
+  bool slow;         // transfer function from the nibble recurrence
   bool conv;
   uint32_t X;
   bool far_cand;
 };
 
 // Module-window masks of a lane.
-__device__ __forceinline__ void lane_window(const Shared& S, Lane& L, int32_t lrel) {
+template <class SH>
+__device__ __forceinline__ void lane_window(const SH& S, Lane& L, int32_t lrel) {
   L.j0 = (S.K == 1) ? 0 : list_find(S, lrel);
   L.bm = 0;
   L.rst = 0;
@@ -548,6 +568,165 @@ __device__ __forceinline__ uint32_t lane_forward(const Lane& L, uint32_t ent) {
   return reach;
 }
 
+// ---- lean lane pipeline of the main pass --------------------------------
+// Lane i of a wave receives the value of lane i-1 (lane 0 gets `first`).
+__device__ __forceinline__ uint32_t wave_shr1(uint32_t x, uint32_t first) {
+  return uint32_t(__builtin_amdgcn_update_dpp(int(first), int(x), 0x138, 0xF, 0xF, false));
+}
+
+// Inclusive wave sum over lanes 0..i (row shifts within 16-lane rows, then
+// row broadcasts of lanes 15 and 31).
+__device__ __forceinline__ uint32_t wave_incl_sum(uint32_t x) {
+  x += uint32_t(__builtin_amdgcn_update_dpp(0, int(x), 0x111, 0xF, 0xF, false));
+  x += uint32_t(__builtin_amdgcn_update_dpp(0, int(x), 0x112, 0xF, 0xF, false));
+  x += uint32_t(__builtin_amdgcn_update_dpp(0, int(x), 0x114, 0xF, 0xF, false));
+  x += uint32_t(__builtin_amdgcn_update_dpp(0, int(x), 0x118, 0xF, 0xF, false));
+  x += uint32_t(__builtin_amdgcn_update_dpp(0, int(x), 0x142, 0xA, 0xF, false));
+  x += uint32_t(__builtin_amdgcn_update_dpp(0, int(x), 0x143, 0xC, 0xF, false));
+  return x;
+}
+
+// Candidate starts of a lane: grammar lookups of all 16 positions (kept in
+// e[] for the result-ID roles), plausibility, long (word count >= 15) and
+// string-operand candidates.
+template <bool kBounds, class SH>
+__device__ __forceinline__ void lane_scan(const SH& S, const VParams& P, Lane& L, uint32_t (&e)[kLaneWords]) {
+#pragma unroll
+  for (int p = 0; p < kLaneWords; ++p) e[p] = tbl_lookup(S.tbl, L.w[p] & 0xFFFFu);
+  uint32_t pl_m = 0, far_m = 0, name_m = 0;
+#pragma unroll
+  for (int p = 0; p < kLaneWords; ++p) {
+    const uint32_t wc = L.w[p] >> 16;
+    bool pl = tbl_plausible(e[p], wc);
+    if (kBounds) {
+      uint64_t span = (wc >= 2) ? ((wc - 1 >= 40) ? ~0ull : ((1ull << (wc - 1)) - 1ull)) : 0ull;
+      pl = pl && ((((uint64_t)L.bm >> (p + 1)) & span) == 0);
+      pl = pl && !((L.hdr >> p) & 1u);
+    }
+    pl_m |= uint32_t(pl) << p;
+    far_m |= uint32_t(pl && wc >= 15u) << p;
+    name_m |= ((e[p] >> 7) & 1u) << p;
+  }
+  L.far_cand = false;
+  if (far_m) {
+    uint32_t fm = far_m;
+    while (fm) {
+      const int p = __builtin_ctz(fm);
+      fm &= fm - 1;
+      const int64_t pos = L.a + p;
+      const uint32_t wc = P.words[pos] >> 16;
+      const int jm = kBounds ? lane_mod_at(L, p) : L.j0;
+      bool ok = pos + int64_t(wc) <= S.list[jm].end;
+      const uint32_t lim = wc - 1 < 18u ? wc - 1 : 18u;
+      for (uint32_t k = 2; ok && k < lim; ++k) {
+        uint32_t x = P.words[pos + k];
+        ok = ((x - 0x01010101u) & ~x & 0x80808080u) == 0;
+      }
+      if (!ok) {
+        pl_m &= ~(1u << p);
+        far_m &= ~(1u << p);
+      }
+    }
+    L.far_cand = far_m != 0;
+  }
+  L.plmask = pl_m;
+  L.farmask = far_m;
+  L.namemask = name_m;
+}
+
+// Lane transfer function by the backward nibble recurrence (lanes with a
+// module start or a long candidate, or whose candidates form more than one
+// chain).
+template <class SH>
+__device__ __forceinline__ void lane_dp_full(const SH& S, Lane& L) {
+  const uint32_t pl_m = L.plmask, far_m = L.farmask;
+  uint64_t R = 0xEDCBA98765432100ull;  // positions 16..30: exit offsets 0..13, 14 = far
+  bool forced = false;
+  uint32_t fval = 0;
+#pragma unroll
+  for (int p = kLaneWords - 1; p >= 0; --p) {
+    const uint32_t wc = L.w[p] >> 16;
+    const bool pl = (pl_m >> p) & 1u;
+    const bool far = (far_m >> p) & 1u;
+    uint32_t val = pl ? (far ? kFar : nib(R, wc & 15u)) : kDead;
+    if ((L.hdr >> p) & 1u) {
+      uint32_t v;
+      if (!((L.rst >> p) & 1u)) {
+        v = kDead;
+      } else {
+        uint32_t hl = S.list[lane_mod_at(L, p)].info & 7u;
+        v = (p + hl < 16u) ? nib(R, hl) : (p + hl - 16u);
+      }
+      forced = true;
+      fval = v;
+      val = v;
+    } else if (forced) {
+      val = fval;
+    }
+    R = (R | val) << 4;
+  }
+  L.F = R >> 4;
+  const uint64_t kNib14 = 0x00FFFFFFFFFFFFFFull, kOnes14 = 0x0011111111111111ull;
+  uint64_t f = L.F & kNib14;
+  if (L.hdr) {
+    L.conv = (fval != kFar);
+    L.X = fval;
+    return;
+  }
+  uint64_t nd = ~f & kNib14;
+  uint64_t alive = (nd | (nd >> 1) | (nd >> 2) | (nd >> 3)) & kOnes14;
+  uint64_t xf = (f ^ (kOnes14 * kFar)) & kNib14;
+  uint64_t notfar = (xf | (xf >> 1) | (xf >> 2) | (xf >> 3)) & kOnes14;
+  bool anyfar = notfar != kOnes14;
+  if (alive == 0) {
+    L.conv = true;
+    L.X = kDead;
+  } else {
+    uint32_t X = uint32_t(f >> __builtin_ctzll(alive)) & 15u;
+    uint64_t xd = (f ^ (kOnes14 * X)) & kNib14;
+    uint64_t differ = (xd | (xd >> 1) | (xd >> 2) | (xd >> 3)) & kOnes14;
+    L.conv = !anyfar && (differ & alive) == 0;
+    L.X = X;
+  }
+}
+
+// Transfer function of a lane.  Fast case (no module start in the lane, no
+// long candidate): follow the chain from the first candidate among entry
+// offsets 0..13; when every candidate there lies on that chain, each entry
+// either joins it (same exit) or is not a plausible start (dead), so the
+// lane's exit does not depend on its entry.  Otherwise the nibble
+// recurrence decides.
+template <class SH>
+__device__ __forceinline__ void lane_chain(const SH& S, Lane& L) {
+  L.slow = L.hdr != 0 || L.farmask != 0;
+  if (!L.slow) {
+    const uint32_t pl_m = L.plmask;
+    const uint32_t cand = pl_m & 0x3FFFu;
+    uint32_t reach = cand ? (1u << __builtin_ctz(cand)) : 0u;
+#pragma unroll
+    for (int p = 0; p < kLaneWords; ++p) {
+      const uint32_t go = ((reach & pl_m) >> p) & 1u;
+      reach |= go << ((p + (L.w[p] >> 16)) & 31u);  // word counts <= 14 here: p + wc <= 29
+    }
+    L.reach0 = reach;
+    if ((cand & ~reach) == 0) {
+      const uint32_t beyond = reach >> 16;
+      L.conv = true;
+      L.X = beyond ? uint32_t(__builtin_ctz(beyond)) : kDead;
+    } else {
+      L.slow = true;
+    }
+  }
+  if (L.slow) lane_dp_full(S, L);
+}
+
+// Chain nodes of a fast lane from its exact entry (see lane_forward).
+__device__ __forceinline__ uint32_t fast_reach(const Lane& L, uint32_t ent) {
+  if (ent >= 14u) return 0u;
+  if ((L.reach0 >> ent) & 1u) return L.reach0 & (~0u << ent);
+  return 1u << ent;  // not a plausible start: the chain ends here with an error
+}
+
 __device__ __forceinline__ void report_error(ModState& ms, uint32_t rel, uint32_t code, uint32_t rank) {
   atomicMin(&ms.err_key, ((unsigned long long)rel << 8) | code);
   atomicMin(&ms.err_rank, ((unsigned long long)rel << 32) | rank);
@@ -578,7 +757,7 @@ template <bool kSem, bool kIdx>
 __device__ __forceinline__ void serial_tile(Shared& S, const VParams& P, long long t, int64_t t0, int64_t t1, uint32_t E) {
   // called by the whole block; wave 0 fetches the count prefix, thread 0 walks
   if (threadIdx.x < 64) {
-    uint32_t pre = (P.mod_off[P.tfm[t]] == t0) ? 0u : count_lookback(P, t);
+    uint32_t pre = (P.mod_off[P.tfm[t]] == t0) ? 0u : count_lookback(P, P.tileB, t);
     if (threadIdx.x == 0) S.prefix = pre;
   }
   __syncthreads();
@@ -654,8 +833,8 @@ __device__ __forceinline__ void serial_tile(Shared& S, const VParams& P, long lo
     break;
   }
   uint32_t exitv = (pos >= 0) ? uint32_t(pos - t1) : kExitDead;
-  st_state(&P.tileA[t], kFlagFull | (far ? kFarBit : 0ull) | exitv);
-  st_state(&P.tileB[t], kFlagFull | cnt);
+  st_state(&P.tileA[(t) * kStateStride], kFlagFull | (far ? kFarBit : 0ull) | exitv);
+  st_state(&P.tileB[(t) * kStateStride], kFlagFull | cnt);
 }
 
 }  // namespace
@@ -671,6 +850,9 @@ __global__ __launch_bounds__(256) void k_plan(VParams P, int64_t chunk) {
     P.ctrl[kCtlClaim2] = 0;
     P.ctrl[kCtlPass2] = 0;
     P.ctrl[kCtlSpinErr] = 0;
+    P.ctrl[kCtlMode] = 0;
+    P.ctrl[kCtlClaimR] = 0;
+    P.ctrl[kCtlDoneR] = 0;
   }
   for (int64_t m = gtid; m < P.M; m += nth) {
     int64_t off = P.mod_off[m], end = P.mod_off[m + 1];
@@ -703,9 +885,10 @@ __global__ __launch_bounds__(256) void k_plan(VParams P, int64_t chunk) {
     s.pad[0] = s.pad[1] = 0;
     P.mods[m] = s;
   }
+  for (int64_t b = gtid; b < P.n_tiles / kResolveTiles + 2; b += nth) P.rstate[b * kStateStride] = 0;
   for (int64_t t = gtid; t < P.n_tiles; t += nth) {
-    P.tileA[t] = 0;
-    P.tileB[t] = 0;
+    P.tileA[(t) * kStateStride] = 0;
+    P.tileB[(t) * kStateStride] = 0;
     // module containing word t * T: last m with mod_off[m] <= tT
     int64_t x = t * kTileWords;
     int64_t lo = 0, hi = P.M - 1;
@@ -751,11 +934,296 @@ __global__ __launch_bounds__(256) void k_plan(VParams P, int64_t chunk) {
 }
 
 // ---------------------------------------------------------------------------
+// Chain pass: for every tile, independently of all other tiles, the lane
+// transfer functions, each lane's exact instruction starts and parse-error
+// nodes (every lane but the tile's first, whose entry comes from the previous
+// tile), and a summary: the tile's exit (it does not depend on the tile's
+// entry), the first lane's candidate chain, and the per-module start counts.
+// Tiles this cannot settle (crowded, a long instruction candidate, a chain
+// that stays ambiguous over a whole lane) are flagged, and the batch then
+// takes the single-pass walk.
+struct ChainShared {
+  uint32_t tbl[257];
+  LEnt list[kListMax];
+  int K;
+  int crowded;
+  uint32_t wagg[kWaves];
+  uint32_t wflags[kWaves];
+  uint32_t wcnt[kWaves];
+  uint32_t whead[kWaves];
+  uint32_t bad;
+  LEnt cache;
+  int cache_ok;
+};
+
+__global__ __launch_bounds__(kBlock, 4) void k_chain(VParams P) {
+  __shared__ ChainShared S;
+  if (threadIdx.x == 0) S.cache_ok = 0;
+  init_table(S.tbl);
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6;
+  const int lane = tid & 63;
+  // words of the block's next tile, loaded while this one is worked on
+  uint4 pf[kLaneWords / 4];
+  long long pf_tile = -1;
+  for (long long t = blockIdx.x; t < P.n_tiles; t += gridDim.x) {
+    const int64_t t0 = t * kTileWords;
+    const int64_t t1 = (t0 + kTileWords < P.W) ? t0 + kTileWords : P.W;
+    Lane L;
+    L.a = t0 + int64_t(tid) * kLaneWords;
+    if (L.a + kLaneWords <= P.W) {
+      const uint4* src = reinterpret_cast<const uint4*>(P.words + L.a);
+      const bool have = pf_tile == t;
+#pragma unroll
+      for (int i = 0; i < kLaneWords / 4; ++i) {
+        uint4 v = have ? pf[i] : src[i];
+        L.w[4 * i] = v.x;
+        L.w[4 * i + 1] = v.y;
+        L.w[4 * i + 2] = v.z;
+        L.w[4 * i + 3] = v.w;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < kLaneWords; ++i) L.w[i] = (L.a + i < P.W) ? P.words[L.a + i] : 0u;
+    }
+    __syncthreads();  // the previous tile is done with the shared state
+    if (wave == 0) build_list(S, P, t, t0, t1);
+    if (tid == 0) S.bad = 0;
+    __syncthreads();
+    uint32_t* sum = P.tsum + 4 * t;
+    if (S.crowded) {
+      if (tid == 0) sum[0] = kSumFallback;
+      continue;
+    }
+    const int32_t lrel = tid * kLaneWords;
+    lane_window(S, L, lrel);
+    uint32_t e[kLaneWords];
+    const bool any_bounds = __ballot(L.bm != 0) != 0;
+    if (any_bounds) lane_scan<true>(S, P, L, e);
+    else lane_scan<false>(S, P, L, e);
+    {
+      const long long tn = t + gridDim.x;
+      const int64_t an = tn * kTileWords + int64_t(tid) * kLaneWords;
+      if (tn < P.n_tiles && an + kLaneWords <= P.W) {
+        const uint4* src = reinterpret_cast<const uint4*>(P.words + an);
+#pragma unroll
+        for (int i = 0; i < kLaneWords / 4; ++i) pf[i] = src[i];
+        pf_tile = tn;
+      }
+    }
+    lane_chain(S, L);
+
+    // exits inside each wave, independent of the wave entry where possible
+    bool known = L.conv;
+    uint32_t ex = L.conv ? L.X : 0u;
+    for (;;) {
+      uint32_t pex = wave_shr1(ex, 0u);
+      bool pk = wave_shr1(known ? 1u : 0u, 0u) != 0;
+      bool nw = !known && pk;
+      if (nw) {
+        ex = apply_fn(L.F, pex);
+        known = true;
+      }
+      if (__ballot(nw) == 0) break;
+    }
+    // the tile's first lane must not pass its entry on to the next lane
+    if (wave == 0 && __ballot(!known) != 0 && lane == 0) S.bad = 1;
+    const bool wave_far = __ballot(L.far_cand) != 0;
+    if (lane == 63) S.wagg[wave] = known ? ex : 0xFFu;
+    if (lane == 0) S.wflags[wave] = wave_far ? 1u : 0u;
+    __syncthreads();
+    bool bad = S.bad != 0;
+    for (int w = 0; w < kWaves; ++w) {
+      bad |= S.wflags[w] != 0;
+      if (w >= 1 && S.wagg[w - 1] == 0xFFu) bad = true;
+    }
+    const uint32_t X = S.wagg[kWaves - 1];
+    if (X == 0xFFu || X == kFar) bad = true;
+    if (bad) {
+      if (tid == 0) sum[0] = kSumFallback;
+      continue;
+    }
+    // entries of every lane but the tile's first
+    const uint32_t Ew = (wave == 0) ? kDead : S.wagg[wave - 1];
+    if (lane == 0 && wave > 0 && !known) {
+      ex = apply_fn(L.F, Ew);
+      known = true;
+    }
+    for (;;) {
+      uint32_t pex = wave_shr1(ex, 0u);
+      bool pk = wave_shr1(known ? 1u : 0u, 0u) != 0;
+      bool nw = !known && pk;
+      if (nw) {
+        ex = apply_fn(L.F, pex);
+        known = true;
+      }
+      if (__ballot(nw) == 0) break;
+    }
+    const uint32_t ent = wave_shr1(ex, Ew);
+    uint32_t starts, errs, mask0 = 0;
+    bool ok0 = true;
+    if (tid != 0) {
+      const uint32_t reach = L.slow ? lane_forward(L, ent == kDead ? 99u : ent) : fast_reach(L, ent);
+      starts = reach & L.plmask & ~L.farmask & ~L.hdr & 0xFFFFu;
+      errs = reach & ~L.plmask & ~L.hdr & 0xFFFFu;
+    } else {
+      // first lane: the chain from its entry, up to its first module start,
+      // is kept as a candidate mask (every candidate there on one chain, so an
+      // entry either joins it or is not a plausible start); starts after a
+      // module start do not depend on the entry
+      if (!L.slow) {
+        mask0 = L.reach0 & L.plmask & 0xFFFFu;
+        starts = 0;
+        errs = 0;
+      } else if (L.hdr && L.farmask == 0) {
+        const uint32_t h0 = uint32_t(__builtin_ctz(L.hdr));
+        const uint32_t hm = (1u << h0) - 1u;
+        const uint32_t cand = L.plmask & 0x3FFFu & hm;
+        uint32_t reach = cand ? (1u << __builtin_ctz(cand)) : 0u;
+#pragma unroll
+        for (int p = 0; p < kLaneWords; ++p) {
+          const uint32_t go = ((reach & L.plmask & hm) >> p) & 1u;
+          reach |= go << ((p + (L.w[p] >> 16)) & 31u);
+        }
+        ok0 = (cand & ~reach) == 0;
+        mask0 = reach & L.plmask & hm;
+        const uint32_t fr = lane_forward(L, 99u);
+        starts = fr & L.plmask & ~L.farmask & ~L.hdr & 0xFFFFu;
+        errs = fr & ~L.plmask & ~L.hdr & 0xFFFFu;
+      } else {
+        ok0 = false;
+        starts = 0;
+        errs = 0;
+      }
+    }
+    // per-module counts: segmented by module starts (as in the main pass)
+    const uint32_t rst = L.rst;
+    const uint32_t nst = __popc(starts);
+    uint32_t cval;
+    if (rst) {
+      int last = 31 - __builtin_clz(rst);
+      cval = 0x80000000u | uint32_t(__popc(starts & ~((2u << last) - 1u)));
+    } else {
+      cval = nst;
+    }
+    uint32_t inc = cval;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      uint32_t u = __shfl_up(inc, d);
+      if (lane >= d) inc = (inc & 0x80000000u) ? inc : (inc + (u & 0x7FFFFFFFu)) | (u & 0x80000000u);
+    }
+    const uint32_t excl = wave_shr1(inc, 0u);
+    if (lane == 63) S.wcnt[wave] = inc;
+    if (tid == 0 && !ok0) S.bad = 1;
+    __syncthreads();
+    if (S.bad) {
+      if (tid == 0) sum[0] = kSumFallback;
+      continue;
+    }
+    uint32_t wpre = 0, tot = 0;
+    for (int w = 0; w < kWaves; ++w) {
+      uint32_t v = S.wcnt[w];
+      if (w < wave) wpre = (v & 0x80000000u) ? v : (wpre + v) | (wpre & 0x80000000u);
+      tot = (v & 0x80000000u) ? v : (tot + v) | (tot & 0x80000000u);
+    }
+    const uint32_t lex = (excl & 0x80000000u) ? excl : (wpre + excl) | (wpre & 0x80000000u);
+    // starts of the module open at the tile start
+    uint32_t head = 0;
+    if (!(lex & 0x80000000u)) head = rst ? uint32_t(__popc(starts & ((1u << __builtin_ctz(rst)) - 1u))) : nst;
+    head = wave_sum_u32(head);
+    if (lane == 0) S.whead[wave] = head;
+    P.lst[t * kBlock + tid] = starts | (errs << 16);
+    __syncthreads();
+    if (tid == 0) {
+      uint32_t c_head = 0;
+      for (int w = 0; w < kWaves; ++w) c_head += S.whead[w];
+      sum[0] = X | ((S.list[0].rel == 0) ? kSumModStart : 0u) | ((tot & 0x80000000u) ? kSumReset : 0u);
+      sum[1] = mask0;
+      sum[2] = c_head;
+      sum[3] = tot & 0x7FFFFFFFu;
+    }
+  }
+}
+
+// Resolve pass: each tile's exact entry (the previous tile's exit) and the
+// count of starts of the module open at its start that lie before it: a
+// segmented scan over the tiles (blocks of kResolveTiles tiles, claimed in
+// order, chained by a decoupled look-back).  The last block to finish sets
+// kCtlMode when no tile was flagged and every exit is a plain offset.
+constexpr int kResolveBlock = kResolveTiles;
+
+__global__ __launch_bounds__(kResolveBlock) void k_resolve(VParams P) {
+  __shared__ uint32_t s_bid;
+  __shared__ uint32_t s_wagg[kResolveBlock / 64];
+  __shared__ uint32_t s_pre;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  if (tid == 0) s_bid = atomicAdd(&P.ctrl[kCtlClaimR], 1u);
+  __syncthreads();
+  const long long bid = s_bid;
+  const long long t = bid * kResolveBlock + tid;
+  const bool real = t < P.n_tiles;
+  const uint4* T = reinterpret_cast<const uint4*>(P.tsum);
+  const uint4 v = real ? T[t] : make_uint4(0u, 0u, 0u, 0u);
+  const uint32_t px = (real && t > 0) ? T[t - 1].x : 0u;
+  bool bad = false;
+  uint32_t E = kExitDead;
+  if (real && !(v.x & kSumModStart) && t > 0) {
+    E = px & 0xFFu;
+    if (px & kSumFallback) bad = true;
+    if (E == kDead) E = kExitDead;
+    else if (E >= kFar) bad = true;
+  }
+  if (real && (v.x & kSumFallback)) bad = true;
+  const uint32_t c0 = (E < 14u && ((v.y >> E) & 1u)) ? uint32_t(__popc(v.y >> E)) : 0u;
+  const bool rs = real && (v.x & kSumReset);
+  const uint32_t val = real ? (rs ? v.w : v.z + c0) : 0u;
+  // inclusive segmented scan (bit 31: a module starts in the range)
+  uint32_t inc = (rs ? 0x80000000u : 0u) | val;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    uint32_t u = __shfl_up(inc, d);
+    if (lane >= d) inc = (inc & 0x80000000u) ? inc : (inc + (u & 0x7FFFFFFFu)) | (u & 0x80000000u);
+  }
+  if (lane == 63) s_wagg[wave] = inc;
+  __syncthreads();
+  uint32_t wpre = 0, btot = 0;
+  for (int w = 0; w < kResolveBlock / 64; ++w) {
+    uint32_t a = s_wagg[w];
+    if (w < wave) wpre = (a & 0x80000000u) ? a : (wpre + a) | (wpre & 0x80000000u);
+    btot = (a & 0x80000000u) ? a : (btot + a) | (btot & 0x80000000u);
+  }
+  if (tid == 64)
+    st_state(&P.rstate[bid * kStateStride], kFlagAgg | ((btot & 0x80000000u) ? kResetBit : 0ull) | (btot & 0x7FFFFFFFu));
+  if (wave == 0) {
+    const uint32_t pre = count_lookback(P, P.rstate, bid);
+    if (lane == 0) {
+      s_pre = pre;
+      const uint32_t incl = (btot & 0x80000000u) ? (btot & 0x7FFFFFFFu) : pre + btot;
+      st_state(&P.rstate[bid * kStateStride], kFlagFull | incl);
+    }
+  }
+  const bool any_bad = __syncthreads_or(bad);
+  // exclusive value of this tile within the block, then with the block prefix
+  uint32_t ex = wave_shr1(inc, 0u);
+  ex = (ex & 0x80000000u) ? ex : (wpre + ex) | (wpre & 0x80000000u);
+  const uint32_t prefix = (ex & 0x80000000u) ? (ex & 0x7FFFFFFFu) : s_pre + ex;
+  if (real) reinterpret_cast<uint2*>(P.tres)[t] = make_uint2(E, (v.x & kSumModStart) ? 0u : prefix);
+  if (tid == 0) {
+    const uint32_t old = atomicAdd(&P.ctrl[kCtlDoneR], 1u + (any_bad ? (1u << 20) : 0u));
+    if ((old & 0xFFFFFu) == gridDim.x - 1 && (old >> 20) == 0 && !any_bad) P.ctrl[kCtlMode] = kModeResolved;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // main pass: boundary recovery, parse checks, instruction index, result-ID
 // checks.
-template <bool kSem, bool kIdx>
-__global__ __launch_bounds__(kBlock, 4) void k_main(VParams P) {
-  __shared__ Shared S;
+// kRes: entries and count prefixes come from the resolve pass (tiles in
+// block order, no look-back, no waiting on other tiles); otherwise the
+// single-pass walk with decoupled look-back.
+template <bool kSem, bool kIdx, bool kRes>
+__device__ __forceinline__ void main_body(Shared& S, const VParams& P) {
   if (threadIdx.x == 0) S.cache_ok = 0;
   init_table(S.tbl);
   const int tid = threadIdx.x;
@@ -763,14 +1231,24 @@ __global__ __launch_bounds__(kBlock, 4) void k_main(VParams P) {
   const int lane = tid & 63;
   // the first tile is claimed here, each later one near the end of the tile
   // before it
-  if (tid == 0) S.tnext = atomicAdd(&P.ctrl[kCtlClaim], 1u);
+  if (tid == 0)
+    S.tnext = (kRes || P.sched_static) ? (long long)blockIdx.x : (long long)atomicAdd(&P.ctrl[kCtlClaim], 1u);
   // result-ID window flush of the previous tile: issued at its end, its
   // returned words are examined at the start of the next tile
   unsigned long long fl_old = 0, fl_bits = 0;
   int64_t fl_mod = -1;
+  // new result IDs of the window are counted per block and added to the
+  // module's count when the module changes or the block ends (one device
+  // atomic per module run instead of one per tile)
+  int64_t dc_mod = -1;
+  uint32_t dc_cnt = 0;
   // words of the next tile, loaded during the tail of the current one
   uint4 pf[kLaneWords / 4];
   long long pf_tile = -1;
+  // resolved walk: the next tile's lane record, entry, prefix and first-lane
+  // chain, loaded with its words
+  uint32_t pr_rec = 0, pr_E = kExitDead, pr_pre = 0, pr_m0 = 0;
+  long long pr_tile = -1;
 
   for (;;) {
     __syncthreads();
@@ -779,15 +1257,22 @@ __global__ __launch_bounds__(kBlock, 4) void k_main(VParams P) {
     if (kSem && fl_mod >= 0) {
       uint32_t cnt = 0;
       bool dup = false;
-      if (tid < kWinWords && fl_bits) {
+      if (tid >= kBlock - kWinWords && fl_bits) {
         dup = (fl_old & fl_bits) != 0;
         cnt = uint32_t(__popcll(fl_bits & ~fl_old));
       }
-      if (wave < kWinWords / 64) {
+      if (wave >= kWaves - kWinWords / 64) {
         cnt = wave_sum_u32(cnt);
         bool d = __ballot(dup) != 0;
         if (lane == 0) {
-          if (cnt) atomicAdd(&P.mods[fl_mod].def_count, cnt);
+          if (cnt) {
+            if (fl_mod != dc_mod) {
+              if (dc_cnt) atomicAdd(&P.mods[dc_mod].def_count, dc_cnt);
+              dc_mod = fl_mod;
+              dc_cnt = 0;
+            }
+            dc_cnt += cnt;
+          }
           if (d) atomicOr(&P.mods[fl_mod].flags, kModDup);
         }
       }
@@ -828,16 +1313,27 @@ __global__ __launch_bounds__(kBlock, 4) void k_main(VParams P) {
       S.slot0[tid] = 0xFFFFFFFFu;
     }
     if (kSem && tid < kWinWords) S.win[tid] = 0;
-    if (tid == 0) S.serial = 0;
+    if (tid < kTileWords / 32) S.badb[tid] = 0;
+    if (tid == 0) {
+      S.serial = 0;
+      S.nname = 0;
+    }
     __syncthreads();
+
+    // The next tile: block order (static) or claimed now by the last wave,
+    // whose answer is read before the scans barrier; the next tile's words
+    // are then loaded during the second half of this tile.
+    long long claim_tn = 0;
+    if (tid == kBlock - 1)
+      claim_tn = (kRes || P.sched_static) ? t + gridDim.x : (long long)atomicAdd(&P.ctrl[kCtlClaim], 1u);
 
     // Every way into the serial path leaves the block below with go_serial
     // set (one call site keeps a single inlined copy of it).
     uint32_t serialE = kExitDead;
     bool go_serial = false;
     do {
-    if (S.crowded) {
-      if (tid == 0) st_state(&P.tileA[t], kFlagAgg | kFarBit | kFar);
+    if (!kRes && S.crowded) {
+      if (tid == 0) st_state(&P.tileA[(t) * kStateStride], kFlagAgg | kFarBit | kFar);
       if (wave == 0) serialE = (S.list[0].rel == 0) ? kExitDead : entry_lookback(P, t);
       go_serial = true;
       break;
@@ -852,118 +1348,197 @@ __global__ __launch_bounds__(kBlock, 4) void k_main(VParams P) {
     }
     const int32_t lrel = tid * kLaneWords;
     lane_window(S, L, lrel);
-    const bool any_bounds = __ballot(L.bm != 0) != 0;
-    if (any_bounds) lane_dp<true>(S, P, L);
-    else lane_dp<false>(S, P, L);
+    uint32_t e[kLaneWords];
+    uint32_t starts, errs;
+    uint32_t reach = 0, ent = 0, E = kExitDead;
+    uint32_t res_pre = 0;
+    if constexpr (kRes) {
+      // starts and parse-error nodes from the chain pass; the first lane adds
+      // the part of its candidate chain that its resolved entry reaches
+      const bool pr = pr_tile == t;
+      const uint32_t rec = pr ? pr_rec : P.lst[t * kBlock + tid];
+      res_pre = pr ? pr_pre : P.tres[2 * t + 1];
+      starts = rec & 0xFFFFu;
+      errs = rec >> 16;
+      if (tid == 0) {
+        const uint32_t Et = pr ? pr_E : P.tres[2 * t];
+        const uint32_t m0 = pr ? pr_m0 : P.tsum[4 * t + 1];
+        const uint32_t h0 = L.hdr ? uint32_t(__builtin_ctz(L.hdr)) : 16u;
+        if (Et < 14u && Et < h0) {
+          if ((m0 >> Et) & 1u) starts |= m0 & (~0u << Et);
+          else errs |= 1u << Et;
+        }
+      }
+    } else {
+      const bool any_bounds = __ballot(L.bm != 0) != 0;
+      if (any_bounds) lane_scan<true>(S, P, L, e);
+      else lane_scan<false>(S, P, L, e);
+      lane_chain(S, L);
 
-    // ---- wave-level resolution independent of the wave entry
-    bool known = L.conv;
-    uint32_t ex = L.conv ? L.X : 0u;
-    for (;;) {
-      uint32_t pex = __shfl_up(ex, 1);
-      bool pk = __shfl_up(known ? 1 : 0, 1) != 0 && lane > 0;
-      bool nw = !known && pk;
-      if (nw) {
-        ex = apply_fn(L.F, pex);
+      // ---- wave-level resolution independent of the wave entry
+      bool known = L.conv;
+      uint32_t ex = L.conv ? L.X : 0u;
+      for (;;) {
+        uint32_t pex = wave_shr1(ex, 0u);
+        bool pk = wave_shr1(known ? 1u : 0u, 0u) != 0;
+        bool nw = !known && pk;
+        if (nw) {
+          ex = apply_fn(L.F, pex);
+          known = true;
+        }
+        if (__ballot(nw) == 0) break;
+      }
+      const bool wave_far = __ballot(L.far_cand) != 0;
+      if (lane == 63) S.wagg[wave] = known ? ex : 0xFFu;
+      if (lane == 0) S.wflags[wave] = wave_far ? 1u : 0u;
+      __syncthreads();
+
+      // ---- tile aggregate (published from wave 1: wave 0's polls below then
+      // do not wait for this store to complete)
+      if (tid == 64) {
+        bool any_far = false, serial = false;
+        for (int w = 0; w < kWaves; ++w) {
+          any_far |= (S.wflags[w] & 1u) != 0;
+          if (w >= 1 && S.wagg[w - 1] == 0xFFu) serial = true;  // a wave entry that needs the previous wave's entry
+        }
+        uint32_t X = S.wagg[kWaves - 1];
+        uint32_t agg = (serial || any_far || X == 0xFFu || X == kFar) ? kFar : X;
+        st_state(&P.tileA[(t) * kStateStride], kFlagAgg | (any_far ? kFarBit : 0ull) | agg);
+        S.serial = serial ? 1 : 0;
+      }
+      // ---- exact tile entry
+      if (wave == 0) {
+        uint32_t E = (S.list[0].rel == 0) ? kExitDead : entry_lookback(P, t);
+        if (lane == 0) S.E = E;
+      }
+      __syncthreads();
+      E = S.E;
+      if (S.serial || (E != kExitDead && E >= kFar)) {
+        serialE = E;
+        go_serial = true;
+        break;
+      }
+
+      // ---- entries of every lane
+      uint32_t Ew = (wave == 0) ? (E == kExitDead ? kDead : E) : S.wagg[wave - 1];
+      if (lane == 0 && !known) {
+        ex = apply_fn(L.F, Ew);
         known = true;
       }
-      if (__ballot(nw) == 0) break;
-    }
-    const bool wave_far = __ballot(L.far_cand) != 0;
-    if (lane == 63) S.wagg[wave] = known ? ex : 0xFFu;
-    if (lane == 0) S.wflags[wave] = wave_far ? 1u : 0u;
-    __syncthreads();
-
-    // ---- tile aggregate
-    if (tid == 0) {
-      bool any_far = false, serial = false;
-      for (int w = 0; w < kWaves; ++w) {
-        any_far |= (S.wflags[w] & 1u) != 0;
-        if (w >= 1 && S.wagg[w - 1] == 0xFFu) serial = true;  // a wave entry that needs the previous wave's entry
+      for (;;) {
+        uint32_t pex = wave_shr1(ex, 0u);
+        bool pk = wave_shr1(known ? 1u : 0u, 0u) != 0;
+        bool nw = !known && pk;
+        if (nw) {
+          ex = apply_fn(L.F, pex);
+          known = true;
+        }
+        if (__ballot(nw) == 0) break;
       }
-      uint32_t X = S.wagg[kWaves - 1];
-      uint32_t agg = (serial || any_far || X == 0xFFu || X == kFar) ? kFar : X;
-      st_state(&P.tileA[t], kFlagAgg | (any_far ? kFarBit : 0ull) | agg);
-      S.serial = serial ? 1 : 0;
+      ent = wave_shr1(ex, Ew);
+      reach = L.slow ? lane_forward(L, ent == kDead ? 99u : ent) : fast_reach(L, ent);
+      const uint32_t hdr = L.hdr;
+      starts = uint32_t(reach) & L.plmask & ~L.farmask & ~hdr & 0xFFFFu;
+      errs = uint32_t(reach) & ~L.plmask & ~hdr & 0xFFFFu;
     }
-    // ---- exact tile entry
-    if (wave == 0) {
-      uint32_t E = (S.list[0].rel == 0) ? kExitDead : entry_lookback(P, t);
-      if (lane == 0) S.E = E;
-    }
-    __syncthreads();
-    const uint32_t E = S.E;
-    if (S.serial || (E != kExitDead && E >= kFar)) {
-      serialE = E;
-      go_serial = true;
-      break;
-    }
-
-    // ---- entries of every lane
-    uint32_t Ew = (wave == 0) ? (E == kExitDead ? kDead : E) : S.wagg[wave - 1];
-    if (lane == 0 && !known) {
-      ex = apply_fn(L.F, Ew);
-      known = true;
-    }
-    for (;;) {
-      uint32_t pex = __shfl_up(ex, 1);
-      bool pk = __shfl_up(known ? 1 : 0, 1) != 0 && lane > 0;
-      bool nw = !known && pk;
-      if (nw) {
-        ex = apply_fn(L.F, pex);
-        known = true;
+    // ID slots of this lane's instructions (bit q <-> word q of the lane
+    // window; words 16..19 belong to the next lane)
+    uint32_t defm = 0, usem = 0;
+    if (kSem && !kRes) {
+#pragma unroll
+      for (int p = 0; p < kLaneWords; ++p) {
+        if ((starts >> p) & 1u) {
+          defm |= ((e[p] >> 24) & 0xFu) << (p + 1);
+          usem |= (e[p] >> 28) << (p + 1);
+        }
       }
-      if (__ballot(nw) == 0) break;
+      S.spill[tid] = ((defm >> 16) & 0xFu) | (((usem >> 16) & 0xFu) << 4);
     }
-    uint32_t ent = __shfl_up(ex, 1);
-    if (lane == 0) ent = Ew;
-    const uint32_t reach = lane_forward(L, ent == kDead ? 99u : ent);
-    const uint32_t hdr = L.hdr;
-    const uint32_t starts = uint32_t(reach) & L.plmask & ~L.farmask & ~hdr & 0xFFFFu;
-    const uint32_t errs = uint32_t(reach) & ~L.plmask & ~hdr & 0xFFFFu;
-    const bool far_hit = (uint32_t(reach) & L.farmask & 0xFFFFu) != 0 || ent == kFar;
-    if (__syncthreads_or(far_hit)) {
-      serialE = E;
-      go_serial = true;
-      break;
+    // a long instruction on the chain sends the tile to the serial path; only
+    // tiles with a long candidate can have one
+    uint32_t tile_far = 0;
+    if (!kRes) {
+#pragma unroll
+      for (int w = 0; w < kWaves; ++w) tile_far |= S.wflags[w];
     }
-    if (tid == kBlock - 1) {
+    if (tile_far != 0) {
+      const bool far_hit = (uint32_t(reach) & L.farmask & 0xFFFFu) != 0 || ent == kFar;
+      if (__syncthreads_or(far_hit)) {
+        serialE = E;
+        go_serial = true;
+        break;
+      }
+    }
+    // OpName starts are compacted for the string checks
+    if (!kRes) {
+      uint32_t ns = starts & L.namemask;
+      if (ns) {
+        uint32_t b = atomicAdd(&S.nname, uint32_t(__popc(ns)));
+        while (ns) {
+          const int p = __builtin_ctz(ns);
+          ns &= ns - 1;
+          S.stage[b++] = uint32_t(lrel + p);
+        }
+      }
+    }
+    if (!kRes && tid == kBlock - 1) {
       // the tile's exit: chain node of the last lane beyond position 15
       uint32_t beyond = reach >> 16;
       uint32_t xv = beyond ? uint32_t(__builtin_ctz(beyond)) : kExitDead;
       if (xv != kExitDead && xv >= 14u) xv = kExitDead;  // the sink
-      st_state(&P.tileA[t],
-               kFlagFull | (S.wflags[0] | S.wflags[1] | S.wflags[2] | S.wflags[3] ? kFarBit : 0ull) | xv);
+      st_state(&P.tileA[(t) * kStateStride],
+               kFlagFull | (tile_far ? kFarBit : 0ull) | xv);
     }
 
     // ---- scans over lanes: per-module instruction counts (segmented by
     // module starts) and tile-local staging slots (plain)
     const uint32_t rst = L.rst;
     const uint32_t nst = __popc(starts);
-    uint32_t cval;
-    if (rst) {
-      int last = 31 - __builtin_clz(rst);
-      cval = 0x80000000u | uint32_t(__popc(starts & ~((2u << last) - 1u)));
-    } else {
-      cval = nst;
-    }
-    uint32_t inc = cval, sinc = nst;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      uint32_t u = __shfl_up(inc, d);
-      uint32_t us = __shfl_up(sinc, d);
-      if (lane >= d) {
-        inc = (inc & 0x80000000u) ? inc : (inc + (u & 0x7FFFFFFFu)) | (u & 0x80000000u);
-        sinc += us;
+    const uint32_t sinc = wave_incl_sum(nst);
+    uint32_t inc, excl;
+    if (S.K > 1 || S.list[0].rel >= 0) {
+      // a module starts in the tile: counts restart at module starts
+      uint32_t cval;
+      if (rst) {
+        int last = 31 - __builtin_clz(rst);
+        cval = 0x80000000u | uint32_t(__popc(starts & ~((2u << last) - 1u)));
+      } else {
+        cval = nst;
       }
+      inc = cval;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        uint32_t u = __shfl_up(inc, d);
+        if (lane >= d) inc = (inc & 0x80000000u) ? inc : (inc + (u & 0x7FFFFFFFu)) | (u & 0x80000000u);
+      }
+      excl = wave_shr1(inc, 0u);
+    } else {
+      inc = sinc;
+      excl = sinc - nst;
     }
-    uint32_t excl = __shfl_up(inc, 1);
-    if (lane == 0) excl = 0;
     if (lane == 63) {
       S.wcnt[wave] = inc;
       S.wst[wave] = sinc;
     }
+    if (tid == kBlock - 1) S.tnext = claim_tn;
     __syncthreads();
+    {
+      const long long tn = S.tnext;
+      const int64_t an = tn * kTileWords + int64_t(tid) * kLaneWords;
+      if (tn < P.n_tiles && an + kLaneWords <= P.W) {
+        const uint4* src = reinterpret_cast<const uint4*>(P.words + an);
+#pragma unroll
+        for (int i = 0; i < kLaneWords / 4; ++i) pf[i] = src[i];
+        pf_tile = tn;
+      }
+      if (kRes && tn < P.n_tiles) {
+        pr_rec = P.lst[tn * kBlock + tid];
+        pr_E = P.tres[2 * tn];
+        pr_pre = P.tres[2 * tn + 1];
+        pr_m0 = P.tsum[4 * tn + 1];
+        pr_tile = tn;
+      }
+    }
     uint32_t wpre = 0, tot = 0, sbase = sinc - nst, n_slots = 0;
     for (int w = 0; w < kWaves; ++w) {
       uint32_t v = S.wcnt[w];
@@ -974,8 +1549,8 @@ __global__ __launch_bounds__(kBlock, 4) void k_main(VParams P) {
       tot = (v & 0x80000000u) ? v : (tot + v) | (tot & 0x80000000u);
       n_slots += S.wst[w];
     }
-    if (tid == 0)
-      st_state(&P.tileB[t], kFlagAgg | ((tot & 0x80000000u) ? kResetBit : 0ull) | (tot & 0x7FFFFFFFu));
+    if (!kRes && tid == 64)
+      st_state(&P.tileB[(t) * kStateStride], kFlagAgg | ((tot & 0x80000000u) ? kResetBit : 0ull) | (tot & 0x7FFFFFFFu));
     // starts of the module open at this lane's start, before it, inside this
     // tile; for list entry 0 the tile prefix is added once it is known
     const uint32_t lex = (excl & 0x80000000u) ? excl : (wpre + excl) | (wpre & 0x80000000u);
@@ -991,15 +1566,13 @@ __global__ __launch_bounds__(kBlock, 4) void k_main(VParams P) {
     // is the start at p in list entry 0 (ranks continue the tile prefix)?
     auto in_first = [&](int p) -> bool { return lane_in_first && (rst & ((2u << p) - 1u)) == 0; };
 
-    // ---- OpName strings (checked on the LDS copy; reported after the ranks
-    // are known)
-    uint32_t bad_names = 0;
-    {
-      uint32_t ns = starts & L.namemask;
-      while (ns) {
-        int p = __builtin_ctz(ns);
-        ns &= ns - 1;
-        const int q = lrel + p;
+    // ---- OpName strings: one lane per compacted start, on the LDS copy of
+    // the words; malformed ones are marked in badb and reported with the
+    // parse errors
+    auto check_names = [&]() {
+      const uint32_t nn = S.nname;
+      for (uint32_t i = tid; i < nn; i += kBlock) {
+        const int q = int(S.stage[i]);
         const uint32_t nw = (S.tw[q] >> 16) - 2;  // string words: 1..12 on this path
         uint32_t x[12];
 #pragma unroll
@@ -1014,84 +1587,126 @@ __global__ __launch_bounds__(kBlock, 4) void k_main(VParams P) {
         }
         uint32_t z = (last - 0x01010101u) & ~last & 0x80808080u;
         ok = ok && z != 0 && (last >> (8 * (__builtin_ctz(z | 0x80000000u) >> 3))) == 0;
-        if (!ok) bad_names |= 1u << p;
+        if (!ok) atomicOr(&S.badb[q >> 5], 1u << (q & 31));
+      }
+    };
+    if (!kRes) check_names();
+
+    // resolved walk: one pass over the lane's starts for the grammar entry,
+    // the ID slots, the OpName marks and the instruction index (the tile
+    // prefix is already known)
+    if constexpr (kRes) {
+      uint32_t name_m = 0;
+      uint32_t sm = starts;
+      uint32_t k = 0;
+      while (sm) {
+        const int p = __builtin_ctz(sm);
+        sm &= sm - 1;
+        const uint32_t w0 = S.tw[lrel + p];
+        const uint32_t ee = tbl_lookup(S.tbl, w0 & 0xFFFFu);
+        name_m |= ((ee >> 7) & 1u) << p;
+        if (kSem) {
+          defm |= ((ee >> 24) & 0xFu) << (p + 1);
+          usem |= (ee >> 28) << (p + 1);
+        }
+        if (kIdx) {
+          int jm;
+          uint32_t rank;
+          if (rst == 0) {
+            jm = L.j0;
+            rank = pre_local + k + (lane_in_first ? res_pre : 0u);
+          } else {
+            jm = lane_mod_at(L, p);
+            rank = rank_local(p) + (in_first(p) ? res_pre : 0u);
+          }
+          const LEnt& le = S.list[jm];
+          if (le.info & kInfoHdrOk) {
+            const int64_t dst = le.off + rank;
+            P.idx_off[dst] = uint32_t(t0 + lrel + p - le.off);
+            P.idx_op[dst] = uint16_t(w0 & 0xFFFFu);
+          }
+        }
+        ++k;
+      }
+      if (kSem) S.spill[tid] = ((defm >> 16) & 0xFu) | (((usem >> 16) & 0xFu) << 4);
+      uint32_t ns = name_m;
+      if (ns) {
+        uint32_t b = atomicAdd(&S.nname, uint32_t(__popc(ns)));
+        while (ns) {
+          const int p = __builtin_ctz(ns);
+          ns &= ns - 1;
+          S.stage[b++] = uint32_t(lrel + p);
+        }
+      }
+      if (!kSem) {
+        __syncthreads();
+        check_names();
       }
     }
 
     // ---- result-ID checks
     if (kSem) {
-      uint32_t defm = 0, usem = 0;
-#pragma unroll
-      for (int p = 0; p < kLaneWords; ++p) {
-        if ((starts >> p) & 1u) {
-          uint32_t r = (L.rolep[p >> 2] >> (8 * (p & 3))) & 0xFFu;
-          defm |= (r & 0xFu) << (p + 1);
-          usem |= (r >> 4) << (p + 1);
-        }
-      }
-      S.spill[tid] = ((defm >> 16) & 0xFu) | (((usem >> 16) & 0xFu) << 4);
       // LDS window for the result IDs of module jw in this tile: anchored at
       // the first result ID found by the lowest wave that has one
       const int jw = S.jw;
       {
         const uint32_t dw = (L.rst == 0 && L.j0 == jw) ? (defm & 0xFFFFu) : 0u;
-        uint32_t first = 0;
-#pragma unroll
-        for (int p = kLaneWords - 1; p >= 0; --p)
-          if ((dw >> p) & 1u) first = L.w[p];
+        const uint32_t first = dw ? S.tw[lrel + __builtin_ctz(dw)] : 0u;
         uint64_t bal = __ballot(dw != 0);
         uint32_t ref = 0xFFFFFFFFu;
         if (bal) ref = __shfl(first, int(__builtin_ctzll(bal)));
         if (lane == 0) S.wref[wave] = ref;
       }
       __syncthreads();
+      if (kRes) check_names();
       if (tid > 0) {
         uint32_t sp = S.spill[tid - 1];
         defm |= sp & 0xFu;
         usem |= (sp >> 4) & 0xFu;
       }
-      uint32_t idm = (defm | usem) & 0xFFFFu;
+      defm &= 0xFFFFu;
+      usem &= 0xFFFFu;
       uint32_t ref = 0xFFFFFFFFu;
       for (int w = kWaves - 1; w >= 0; --w)
         if (S.wref[w] != 0xFFFFFFFFu) ref = S.wref[w];
       const bool win_on = jw >= 0 && ref != 0xFFFFFFFFu;
       const uint32_t base64 = (ref > 2048u ? ref - 2048u : 0u) & ~63u;
-      // Hot loop: bound check and LDS-window insertion for lanes whose whole
-      // segment belongs to one module; every other ID word (result outside
-      // the window, hash-mode module, lanes with a module start) is collected
-      // in `rare` and handled below.
+      // Lanes inside one bitmap-mode module: bound check of every ID word,
+      // LDS-window insertion of the result IDs.  Every other ID word (result
+      // outside the window, hash-mode module, lanes with a module start) is
+      // collected in `rare` and handled below.
       uint32_t rare = 0;
       if (L.rst == 0) {
         const int j0 = L.j0;
         const uint32_t info = S.list[j0].info, bound = S.list[j0].bound;
         if ((info & kInfoHdrOk) && !(info & kInfoSparse)) {
-          const bool win_here = win_on && j0 == jw;
-          bool oob = false, dup = false;
+          const uint32_t bm1 = bound ? bound - 1u : 0u;  // v - 1 >= bm1  <=>  v == 0 or v >= bound
+          const uint32_t idm = defm | usem;
+          bool oob = false;
 #pragma unroll
-          for (int p = 0; p < kLaneWords; ++p) {
-            if ((idm >> p) & 1u) {
-              uint32_t v = L.w[p];
-              bool is_def = (defm >> p) & 1u;
-              bool bad = v == 0u || v >= bound;
-              oob |= bad;
-              bool in_win = win_here && v - base64 < 64u * kWinWords && v >= base64;
-              if (!bad && is_def) {
-                if (in_win) {
-                  unsigned long long bit = 1ull << (v & 63u);
-                  unsigned long long old = atomicOr(&S.win[(v - base64) >> 6], bit);
-                  dup |= (old & bit) != 0;
-                } else {
-                  rare |= 1u << p;
-                }
-              }
+          for (int p = 0; p < kLaneWords; ++p) oob |= ((idm >> p) & 1u) && (L.w[p] - 1u >= bm1);
+          const bool win_here = win_on && j0 == jw;
+          bool dup = false;
+          uint32_t dm = defm;
+          while (dm) {
+            const int p = __builtin_ctz(dm);
+            dm &= dm - 1;
+            const uint32_t v = S.tw[lrel + p];
+            if (v - 1u >= bm1) continue;  // out of bound: flagged above
+            if (win_here && v >= base64 && v - base64 < 64u * kWinWords) {
+              const unsigned long long bit = 1ull << (v & 63u);
+              const unsigned long long old = atomicOr(&S.win[(v - base64) >> 6], bit);
+              dup |= (old & bit) != 0;
+            } else {
+              rare |= 1u << p;
             }
           }
           if (oob || dup) atomicOr(&S.modflags[j0], (oob ? kModOOB : 0u) | (dup ? kModDup : 0u));
         } else if (info & kInfoHdrOk) {
-          rare = idm;
+          rare = defm | usem;
         }
       } else {
-        rare = idm;
+        rare = defm | usem;
       }
       while (rare) {
         int p = __builtin_ctz(rare);
@@ -1119,16 +1734,26 @@ __global__ __launch_bounds__(kBlock, 4) void k_main(VParams P) {
           if (!(d || u)) continue;
           int jm = lane_mod_at(L, 15);
           const LEnt& le = S.list[jm];
-          if (le.info & kInfoHdrOk) id_check(P, le, S.tw[kTileWords + k], d, &S.modflags[jm], &S.moddef[jm]);
+          if (!(le.info & kInfoHdrOk)) continue;
+          const uint32_t v = S.tw[kTileWords + k];
+          if (d && win_on && jm == jw && v != 0u && v < le.bound && v >= base64 && v - base64 < 64u * kWinWords) {
+            unsigned long long bit = 1ull << (v & 63u);
+            unsigned long long old = atomicOr(&S.win[(v - base64) >> 6], bit);
+            if (old & bit) atomicOr(&S.modflags[jm], kModDup);
+          } else {
+            id_check(P, le, v, d, &S.modflags[jm], &S.moddef[jm]);
+          }
         }
       }
       __syncthreads();
-      // window flush: one device atomic per 64 result IDs; the returned words
-      // are examined at the start of the next tile
+      // window flush: one device atomic per 64 result IDs, issued by the last
+      // waves (wave 0 polls other tiles' states next); the returned words are
+      // examined at the start of the next tile
       fl_mod = win_on ? int64_t(S.list[jw].mod) : -1;
-      if (win_on && tid < kWinWords) {
-        fl_bits = S.win[tid];
-        fl_old = fl_bits ? atomicOr(&P.idmap[S.list[jw].off + (base64 >> 6) + tid], fl_bits) : 0ull;
+      if (win_on && tid >= kBlock - kWinWords) {
+        const int i = tid - (kBlock - kWinWords);
+        fl_bits = S.win[i];
+        fl_old = fl_bits ? atomicOr(&P.idmap[S.list[jw].off + (base64 >> 6) + i], fl_bits) : 0ull;
       }
       if (tid < S.K && S.list[tid].mod >= 0) {
         ModState& ms = P.mods[S.list[tid].mod];
@@ -1138,7 +1763,8 @@ __global__ __launch_bounds__(kBlock, 4) void k_main(VParams P) {
     }
 
     // ---- index entries staged in LDS in tile order (slot = plain scan)
-    if (kIdx) {
+    if (kIdx && !kRes) {
+      if (!kSem) __syncthreads();  // the string checks above read stage[]
 #pragma unroll
       for (int p = 0; p < kLaneWords; ++p) {
         if ((starts >> p) & 1u) S.stage[sbase + __popc(starts & ((1u << p) - 1u))] = uint32_t(lrel + p) | (L.w[p] << 16);
@@ -1160,35 +1786,22 @@ __global__ __launch_bounds__(kBlock, 4) void k_main(VParams P) {
       }
     }
 
-    // ---- tile prefix of list entry 0 (count look-back), inclusive state;
-    // the next tile is claimed now (its latency hides behind the look-back)
-    // so that its words can be loaded during the rest of this tile
-    if (wave == 0) {
-      uint32_t tn = 0;
-      if (lane == 0) tn = atomicAdd(&P.ctrl[kCtlClaim], 1u);
-      uint32_t prefix = (S.list[0].rel == 0) ? 0u : count_lookback(P, t);
+    // ---- tile prefix of list entry 0 (count look-back), inclusive state
+    if (kRes) {
+      if (tid == 0) S.prefix = res_pre;
+    } else if (wave == 0) {
+      uint32_t prefix = (S.list[0].rel == 0) ? 0u : count_lookback(P, P.tileB, t);
       if (lane == 0) {
         S.prefix = prefix;
-        S.tnext = tn;
         uint32_t incl = (tot & 0x80000000u) ? (tot & 0x7FFFFFFFu) : prefix + tot;
-        st_state(&P.tileB[t], kFlagFull | incl);
+        st_state(&P.tileB[(t) * kStateStride], kFlagFull | incl);
       }
     }
     __syncthreads();
     const uint32_t prefix = S.prefix;
-    {
-      const long long tn = S.tnext;
-      const int64_t an = tn * kTileWords + int64_t(tid) * kLaneWords;
-      if (tn < P.n_tiles && an + kLaneWords <= P.W) {
-        const uint4* src = reinterpret_cast<const uint4*>(P.words + an);
-#pragma unroll
-        for (int i = 0; i < kLaneWords / 4; ++i) pf[i] = src[i];
-        pf_tile = tn;
-      }
-    }
 
     // ---- instruction index: coalesced stores of the staged entries
-    if (kIdx) {
+    if (kIdx && !kRes) {
       const int K = S.K;
       for (uint32_t sl = tid; sl < n_slots; sl += kBlock) {
         // modules with starts in this tile own consecutive slot ranges in
@@ -1234,6 +1847,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_main(VParams P) {
     // ---- parse errors: chain nodes that are not valid instructions, and
     // OpName starts whose string is malformed
     {
+      const uint32_t bad_names = (S.badb[lrel >> 5] >> (lrel & 31)) & 0xFFFFu;
       uint32_t ee = errs | bad_names;
       while (ee) {
         int p = __builtin_ctz(ee);
@@ -1250,10 +1864,18 @@ __global__ __launch_bounds__(kBlock, 4) void k_main(VParams P) {
     }
     } while (false);
     if (go_serial) {
-      if (tid == 0) S.tnext = atomicAdd(&P.ctrl[kCtlClaim], 1u);
+      if (tid == kBlock - 1) S.tnext = claim_tn;
       serial_tile<kSem, kIdx>(S, P, t, t0, t1, serialE);
     }
   }
+  if (kSem && dc_cnt) atomicAdd(&P.mods[dc_mod].def_count, dc_cnt);
+}
+
+template <bool kSem, bool kIdx>
+__global__ __launch_bounds__(kBlock, 4) void k_main(VParams P) {
+  __shared__ Shared S;
+  if (P.ctrl[kCtlMode] == kModeResolved) main_body<kSem, kIdx, true>(S, P);
+  else main_body<kSem, kIdx, false>(S, P);
 }
 
 // ---------------------------------------------------------------------------
@@ -1365,8 +1987,9 @@ __global__ __launch_bounds__(kBlock) void k_pass2(VParams P) {
     // bitmap-mode modules: walk the chain from the exact entry and test uses
     uint32_t E;
     if (S.list[0].rel == 0 || t == 0) E = kExitDead;
+    else if (P.ctrl[kCtlMode] == kModeResolved) E = P.tres[2 * t];
     else {
-      unsigned long long st = ld_state(&P.tileA[t - 1]);
+      unsigned long long st = ld_state(&P.tileA[(t - 1) * kStateStride]);
       E = uint32_t(st);
     }
     bool serial = S.crowded || (E != kExitDead && E >= kFar);
@@ -1504,14 +2127,24 @@ void launch_plan(const VParams& p, int grid, hipStream_t s) {
   hipLaunchKernelGGL(k_plan, dim3(grid), dim3(256), 0, s, p, int64_t(16384));
 }
 
-void launch_main(const VParams& p, int grid, hipStream_t s) {
-  if (p.semantic) {
-    if (p.index) hipLaunchKernelGGL((k_main<true, true>), dim3(grid), dim3(kBlock), 0, s, p);
-    else hipLaunchKernelGGL((k_main<true, false>), dim3(grid), dim3(kBlock), 0, s, p);
-  } else {
-    if (p.index) hipLaunchKernelGGL((k_main<false, true>), dim3(grid), dim3(kBlock), 0, s, p);
-    else hipLaunchKernelGGL((k_main<false, false>), dim3(grid), dim3(kBlock), 0, s, p);
-  }
+hipError_t launch_main(const VParams& p, int grid, hipStream_t s) {
+  const void* f = p.semantic ? (p.index ? reinterpret_cast<const void*>(k_main<true, true>)
+                                        : reinterpret_cast<const void*>(k_main<true, false>))
+                             : (p.index ? reinterpret_cast<const void*>(k_main<false, true>)
+                                        : reinterpret_cast<const void*>(k_main<false, false>));
+  VParams q = p;
+  void* args[] = {&q};
+  if (p.sched_static) return hipLaunchCooperativeKernel(f, dim3(grid), dim3(kBlock), args, 0, s);
+  return hipLaunchKernel(f, dim3(grid), dim3(kBlock), args, 0, s);
+}
+
+void launch_chain(const VParams& p, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_chain, dim3(grid), dim3(kBlock), 0, s, p);
+}
+
+void launch_resolve(const VParams& p, hipStream_t s) {
+  int64_t g = p.n_tiles / kResolveTiles + 1;
+  hipLaunchKernelGGL(k_resolve, dim3(int(g)), dim3(kResolveBlock), 0, s, p);
 }
 
 void launch_finalize(const VParams& p, int phase, hipStream_t s) {
@@ -1527,6 +2160,12 @@ void launch_pass2(const VParams& p, int grid, hipStream_t s) {
 }  // namespace spv
 
 namespace spv {
+int chain_occupancy() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(k_chain), kBlock, 0) != hipSuccess)
+    return 0;
+  return n;
+}
 int main_occupancy() {
   int n = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(k_main<true, true>), kBlock, 0) !=
