@@ -589,7 +589,7 @@ __device__ __forceinline__ uint32_t wave_incl_sum(uint32_t x) {
 // Candidate starts of a lane: grammar lookups of all 16 positions (kept in
 // e[] for the result-ID roles), plausibility, long (word count >= 15) and
 // string-operand candidates.
-template <bool kBounds, class SH>
+template <bool kBounds, bool kNames = true, class SH>
 __device__ __forceinline__ void lane_scan(const SH& S, const VParams& P, Lane& L, uint32_t (&e)[kLaneWords]) {
 #pragma unroll
   for (int p = 0; p < kLaneWords; ++p) e[p] = tbl_lookup(S.tbl, L.w[p] & 0xFFFFu);
@@ -605,7 +605,7 @@ __device__ __forceinline__ void lane_scan(const SH& S, const VParams& P, Lane& L
     }
     pl_m |= uint32_t(pl) << p;
     far_m |= uint32_t(pl && wc >= 15u) << p;
-    name_m |= ((e[p] >> 7) & 1u) << p;
+    if (kNames) name_m |= ((e[p] >> 7) & 1u) << p;
   }
   L.far_cand = false;
   if (far_m) {
@@ -956,16 +956,15 @@ struct ChainShared {
   int cache_ok;
 };
 
-__global__ __launch_bounds__(kBlock, 4) void k_chain(VParams P) {
+// (6 waves per SIMD: the pass has little shared state, so more resident
+// blocks hide the load latency of each tile)
+__global__ __launch_bounds__(kBlock, 6) void k_chain(VParams P) {
   __shared__ ChainShared S;
   if (threadIdx.x == 0) S.cache_ok = 0;
   init_table(S.tbl);
   const int tid = threadIdx.x;
   const int wave = tid >> 6;
   const int lane = tid & 63;
-  // words of the block's next tile, loaded while this one is worked on
-  uint4 pf[kLaneWords / 4];
-  long long pf_tile = -1;
   for (long long t = blockIdx.x; t < P.n_tiles; t += gridDim.x) {
     const int64_t t0 = t * kTileWords;
     const int64_t t1 = (t0 + kTileWords < P.W) ? t0 + kTileWords : P.W;
@@ -973,10 +972,9 @@ __global__ __launch_bounds__(kBlock, 4) void k_chain(VParams P) {
     L.a = t0 + int64_t(tid) * kLaneWords;
     if (L.a + kLaneWords <= P.W) {
       const uint4* src = reinterpret_cast<const uint4*>(P.words + L.a);
-      const bool have = pf_tile == t;
 #pragma unroll
       for (int i = 0; i < kLaneWords / 4; ++i) {
-        uint4 v = have ? pf[i] : src[i];
+        uint4 v = src[i];
         L.w[4 * i] = v.x;
         L.w[4 * i + 1] = v.y;
         L.w[4 * i + 2] = v.z;
@@ -999,18 +997,8 @@ __global__ __launch_bounds__(kBlock, 4) void k_chain(VParams P) {
     lane_window(S, L, lrel);
     uint32_t e[kLaneWords];
     const bool any_bounds = __ballot(L.bm != 0) != 0;
-    if (any_bounds) lane_scan<true>(S, P, L, e);
-    else lane_scan<false>(S, P, L, e);
-    {
-      const long long tn = t + gridDim.x;
-      const int64_t an = tn * kTileWords + int64_t(tid) * kLaneWords;
-      if (tn < P.n_tiles && an + kLaneWords <= P.W) {
-        const uint4* src = reinterpret_cast<const uint4*>(P.words + an);
-#pragma unroll
-        for (int i = 0; i < kLaneWords / 4; ++i) pf[i] = src[i];
-        pf_tile = tn;
-      }
-    }
+    if (any_bounds) lane_scan<true, false>(S, P, L, e);
+    else lane_scan<false, false>(S, P, L, e);
     lane_chain(S, L);
 
     // exits inside each wave, independent of the wave entry where possible
@@ -1286,12 +1274,23 @@ __device__ __forceinline__ void main_body(Shared& S, const VParams& P) {
     L.a = t0 + int64_t(tid) * kLaneWords;
     // coalesced 16-byte loads of the lane's 16 words, kept in registers and
     // in LDS (strings and rare paths read the LDS copy)
-    if (L.a + kLaneWords <= P.W) {
-      const uint4* src = reinterpret_cast<const uint4*>(P.words + L.a);
-      const bool have = pf_tile == t;
+    // (pf_tile is the same in every thread, so the prefetched branch is
+    // taken by the whole block)
+    if (pf_tile == t) {
 #pragma unroll
       for (int i = 0; i < kLaneWords / 4; ++i) {
-        uint4 v = have ? pf[i] : src[i];
+        const uint4 v = pf[i];
+        L.w[4 * i] = v.x;
+        L.w[4 * i + 1] = v.y;
+        L.w[4 * i + 2] = v.z;
+        L.w[4 * i + 3] = v.w;
+        *reinterpret_cast<uint4*>(&S.tw[tid * kLaneWords + 4 * i]) = v;
+      }
+    } else if (L.a + kLaneWords <= P.W) {
+      const uint4* src = reinterpret_cast<const uint4*>(P.words + L.a);
+#pragma unroll
+      for (int i = 0; i < kLaneWords / 4; ++i) {
+        const uint4 v = src[i];
         L.w[4 * i] = v.x;
         L.w[4 * i + 1] = v.y;
         L.w[4 * i + 2] = v.z;
@@ -1525,10 +1524,21 @@ __device__ __forceinline__ void main_body(Shared& S, const VParams& P) {
     {
       const long long tn = S.tnext;
       const int64_t an = tn * kTileWords + int64_t(tid) * kLaneWords;
-      if (tn < P.n_tiles && an + kLaneWords <= P.W) {
-        const uint4* src = reinterpret_cast<const uint4*>(P.words + an);
+      if (tn < P.n_tiles) {
+        if (an + kLaneWords <= P.W) {
+          const uint4* src = reinterpret_cast<const uint4*>(P.words + an);
 #pragma unroll
-        for (int i = 0; i < kLaneWords / 4; ++i) pf[i] = src[i];
+          for (int i = 0; i < kLaneWords / 4; ++i) pf[i] = src[i];
+        } else {
+          // the batch's last, partial tile: words past the end read as 0
+#pragma unroll
+          for (int i = 0; i < kLaneWords / 4; ++i) {
+            uint32_t x[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) x[j] = (an + 4 * i + j < P.W) ? P.words[an + 4 * i + j] : 0u;
+            pf[i] = make_uint4(x[0], x[1], x[2], x[3]);
+          }
+        }
         pf_tile = tn;
       }
       if (kRes && tn < P.n_tiles) {
