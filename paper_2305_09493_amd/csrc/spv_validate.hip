@@ -1232,6 +1232,7 @@ __device__ __forceinline__ void main_body(Shared& S, const VParams& P) {
   uint32_t dc_cnt = 0;
   // words of the next tile, loaded during the tail of the current one
   uint4 pf[kLaneWords / 4];
+  uint32_t pf_tail = 0;  // (threads below kTwTail) a word past the next tile's end
   long long pf_tile = -1;
   // resolved walk: the next tile's lane record, entry, prefix and first-lane
   // chain, loaded with its words
@@ -1304,7 +1305,7 @@ __device__ __forceinline__ void main_body(Shared& S, const VParams& P) {
         S.tw[tid * kLaneWords + i] = L.w[i];
       }
     }
-    if (tid < kTwTail) S.tw[kTileWords + tid] = (t1 + tid < P.W) ? P.words[t1 + tid] : 0u;
+    if (tid < kTwTail) S.tw[kTileWords + tid] = (pf_tile == t) ? pf_tail : ((t1 + tid < P.W) ? P.words[t1 + tid] : 0u);
     if (wave == 0) build_list(S, P, t, t0, t1);
     if (tid < kListMax) {
       S.modflags[tid] = 0;
@@ -1538,6 +1539,10 @@ __device__ __forceinline__ void main_body(Shared& S, const VParams& P) {
             for (int j = 0; j < 4; ++j) x[j] = (an + 4 * i + j < P.W) ? P.words[an + 4 * i + j] : 0u;
             pf[i] = make_uint4(x[0], x[1], x[2], x[3]);
           }
+        }
+        if (tid < kTwTail) {
+          const int64_t e1 = (tn + 1) * kTileWords;
+          pf_tail = (e1 + tid < P.W) ? P.words[e1 + tid] : 0u;
         }
         pf_tile = tn;
       }
@@ -1798,7 +1803,7 @@ __device__ __forceinline__ void main_body(Shared& S, const VParams& P) {
 
     // ---- tile prefix of list entry 0 (count look-back), inclusive state
     if (kRes) {
-      if (tid == 0) S.prefix = res_pre;
+      // (all threads hold the prefix)
     } else if (wave == 0) {
       uint32_t prefix = (S.list[0].rel == 0) ? 0u : count_lookback(P, P.tileB, t);
       if (lane == 0) {
@@ -1807,8 +1812,10 @@ __device__ __forceinline__ void main_body(Shared& S, const VParams& P) {
         st_state(&P.tileB[(t) * kStateStride], kFlagFull | incl);
       }
     }
-    __syncthreads();
-    const uint32_t prefix = S.prefix;
+    // the resolved walk with result-ID checks has passed a barrier since the
+    // string checks; the others wait here for the prefix or the string marks
+    if (!kRes || !kSem) __syncthreads();
+    const uint32_t prefix = kRes ? res_pre : S.prefix;
 
     // ---- instruction index: coalesced stores of the staged entries
     if (kIdx && !kRes) {
