@@ -15,6 +15,7 @@ struct spv_ctx {
   int blocks_per_cu;   // persistent grid of the decode/validate kernels
   int occupancy;       // resident blocks per CU of the main kernel
   int chain_occ;       // resident blocks per CU of the chain pass
+  int walk_occ;        // resident blocks per CU of the resolved walk
   int encode_block;    // records per encode block
   hipError_t last;
   char msg[256];
@@ -26,6 +27,7 @@ struct spv_ctx {
 namespace spv {
 int main_occupancy();
 int chain_occupancy();
+int walk_occupancy();
 }
 
 namespace {
@@ -132,6 +134,13 @@ int run_validate(spv_ctx* ctx, const uint32_t* words, const int64_t* mod_off, in
     if ((r = check_launch(ctx))) return r;
     spv::launch_resolve(p, s);
     if ((r = check_launch(ctx))) return r;
+    // resolved walk (returns at once when the resolve pass left the batch to
+    // the single-pass walk, which is launched next and returns at once
+    // otherwise)
+    int64_t wgrid = int64_t(ctx->n_cu) * ctx->walk_occ;
+    if (wgrid > p.n_tiles) wgrid = p.n_tiles;
+    spv::launch_walk(p, int(wgrid), s);
+    if ((r = check_launch(ctx))) return r;
     // Static tile order needs every block resident at once: a cooperative
     // launch guarantees that.  Stream capture keeps the claimed order.
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
@@ -185,6 +194,8 @@ int spv_create(spv_ctx** out, int hip_device) {
     c->occupancy = occ;
     int cocc = spv::chain_occupancy();
     c->chain_occ = cocc > 0 ? cocc : 2;
+    int wocc = spv::walk_occupancy();
+    c->walk_occ = wocc > 0 ? wocc : 2;
     c->blocks_per_cu = occ > 0 ? (occ < 8 ? occ : 8) : 2;
   }
   c->encode_block = 1024;

@@ -173,6 +173,7 @@ struct Params;  // forward
 void launch_plan(const VParams& p, int grid, hipStream_t s);
 hipError_t launch_main(const VParams& p, int grid, hipStream_t s);
 void launch_chain(const VParams& p, int grid, hipStream_t s);
+void launch_walk(const VParams& p, int grid, hipStream_t s);
 void launch_resolve(const VParams& p, hipStream_t s);
 void launch_finalize(const VParams& p, int phase, hipStream_t s);
 void launch_pass2(const VParams& p, int grid, hipStream_t s);

@@ -215,6 +215,38 @@ struct Shared {
   int cache_ok;
 };
 
+// Shared state of the resolved walk: no staging of index entries (they are
+// written directly), OpName starts in a short list (a tile with more checks
+// its strings lane by lane), so that six blocks fit on a CU.
+constexpr int kNameCap = 1024;
+struct WalkShared {
+  uint32_t tw[kTileWords + kTwTail] __attribute__((aligned(16)));
+  uint16_t names[kNameCap];
+  uint32_t tbl[257];
+  LEnt list[kListMax];
+  int K;
+  int crowded;
+  long long t;
+  long long tnext;
+  uint32_t wagg[kWaves];
+  uint32_t wflags[kWaves];
+  uint32_t wcnt[kWaves];
+  uint32_t wst[kWaves];
+  uint32_t wref[kWaves];
+  uint32_t E;
+  uint32_t prefix;
+  int serial;
+  int jw;
+  uint32_t spill[kBlock];
+  uint32_t modflags[kListMax];
+  uint32_t moddef[kListMax];
+  unsigned long long win[kWinWords];
+  uint32_t nname;
+  uint32_t badb[kTileWords / 32];
+  LEnt cache;
+  int cache_ok;
+};
+
 // Build the list of non-empty modules overlapping [t0, t1 + 16] (wave 0).
 template <class SH>
 __device__ __forceinline__ void build_list(SH& S, const VParams& P, long long t, int64_t t0, int64_t t1) {
@@ -1210,8 +1242,8 @@ __global__ __launch_bounds__(kResolveBlock) void k_resolve(VParams P) {
 // kRes: entries and count prefixes come from the resolve pass (tiles in
 // block order, no look-back, no waiting on other tiles); otherwise the
 // single-pass walk with decoupled look-back.
-template <bool kSem, bool kIdx, bool kRes>
-__device__ __forceinline__ void main_body(Shared& S, const VParams& P) {
+template <bool kSem, bool kIdx, bool kRes, class SH>
+__device__ __forceinline__ void main_body(SH& S, const VParams& P) {
   if (threadIdx.x == 0) S.cache_ok = 0;
   init_table(S.tbl);
   const int tid = threadIdx.x;
@@ -1310,7 +1342,7 @@ __device__ __forceinline__ void main_body(Shared& S, const VParams& P) {
     if (tid < kListMax) {
       S.modflags[tid] = 0;
       S.moddef[tid] = 0;
-      S.slot0[tid] = 0xFFFFFFFFu;
+      if constexpr (!kRes) S.slot0[tid] = 0xFFFFFFFFu;
     }
     if (kSem && tid < kWinWords) S.win[tid] = 0;
     if (tid < kTileWords / 32) S.badb[tid] = 0;
@@ -1470,7 +1502,7 @@ __device__ __forceinline__ void main_body(Shared& S, const VParams& P) {
       }
     }
     // OpName starts are compacted for the string checks
-    if (!kRes) {
+    if constexpr (!kRes) {
       uint32_t ns = starts & L.namemask;
       if (ns) {
         uint32_t b = atomicAdd(&S.nname, uint32_t(__popc(ns)));
@@ -1522,7 +1554,10 @@ __device__ __forceinline__ void main_body(Shared& S, const VParams& P) {
     }
     if (tid == kBlock - 1) S.tnext = claim_tn;
     __syncthreads();
-    {
+    // the next tile's words (and, in the resolved walk, its records): the
+    // single-pass walk loads them here; the resolved walk, which runs more
+    // blocks per CU, after its result-ID checks (fewer live registers there)
+    auto issue_prefetch = [&]() {
       const long long tn = S.tnext;
       const int64_t an = tn * kTileWords + int64_t(tid) * kLaneWords;
       if (tn < P.n_tiles) {
@@ -1553,7 +1588,8 @@ __device__ __forceinline__ void main_body(Shared& S, const VParams& P) {
         pr_m0 = P.tsum[4 * tn + 1];
         pr_tile = tn;
       }
-    }
+    };
+    if constexpr (!kRes) issue_prefetch();
     uint32_t wpre = 0, tot = 0, sbase = sinc - nst, n_slots = 0;
     for (int w = 0; w < kWaves; ++w) {
       uint32_t v = S.wcnt[w];
@@ -1584,29 +1620,45 @@ __device__ __forceinline__ void main_body(Shared& S, const VParams& P) {
     // ---- OpName strings: one lane per compacted start, on the LDS copy of
     // the words; malformed ones are marked in badb and reported with the
     // parse errors
-    auto check_names = [&]() {
+    // one OpName start at tile position q: its string, on the LDS copy of the
+    // words; malformed ones are marked in badb and reported with the parse
+    // errors
+    auto check_name = [&](const int q) {
+      const uint32_t nw = (S.tw[q] >> 16) - 2;  // string words: 1..12 on this path
+      uint32_t x[12];
+#pragma unroll
+      for (int k = 0; k < 12; ++k) x[k] = (uint32_t(k) < nw) ? S.tw[q + 2 + k] : 0u;
+      bool ok = true;
+      uint32_t last = 0;
+#pragma unroll
+      for (int k = 0; k < 12; ++k) {
+        uint32_t z = (x[k] - 0x01010101u) & ~x[k] & 0x80808080u;
+        if (uint32_t(k) + 1 < nw) ok = ok && z == 0;
+        if (uint32_t(k) + 1 == nw) last = x[k];
+      }
+      uint32_t z = (last - 0x01010101u) & ~last & 0x80808080u;
+      ok = ok && z != 0 && (last >> (8 * (__builtin_ctz(z | 0x80000000u) >> 3))) == 0;
+      if (!ok) atomicOr(&S.badb[q >> 5], 1u << (q & 31));
+    };
+    auto check_names = [&](uint32_t own) {
       const uint32_t nn = S.nname;
-      for (uint32_t i = tid; i < nn; i += kBlock) {
-        const int q = int(S.stage[i]);
-        const uint32_t nw = (S.tw[q] >> 16) - 2;  // string words: 1..12 on this path
-        uint32_t x[12];
-#pragma unroll
-        for (int k = 0; k < 12; ++k) x[k] = (uint32_t(k) < nw) ? S.tw[q + 2 + k] : 0u;
-        bool ok = true;
-        uint32_t last = 0;
-#pragma unroll
-        for (int k = 0; k < 12; ++k) {
-          uint32_t z = (x[k] - 0x01010101u) & ~x[k] & 0x80808080u;
-          if (uint32_t(k) + 1 < nw) ok = ok && z == 0;
-          if (uint32_t(k) + 1 == nw) last = x[k];
+      if constexpr (kRes) {
+        if (nn <= uint32_t(kNameCap)) {
+          for (uint32_t i = tid; i < nn; i += kBlock) check_name(int(S.names[i]));
+        } else {
+          while (own) {
+            const int p = __builtin_ctz(own);
+            own &= own - 1;
+            check_name(lrel + p);
+          }
         }
-        uint32_t z = (last - 0x01010101u) & ~last & 0x80808080u;
-        ok = ok && z != 0 && (last >> (8 * (__builtin_ctz(z | 0x80000000u) >> 3))) == 0;
-        if (!ok) atomicOr(&S.badb[q >> 5], 1u << (q & 31));
+      } else {
+        for (uint32_t i = tid; i < nn; i += kBlock) check_name(int(S.stage[i]));
       }
     };
-    if (!kRes) check_names();
+    if constexpr (!kRes) check_names(0u);
 
+    uint32_t own_names = 0;
     // resolved walk: one pass over the lane's starts for the grammar entry,
     // the ID slots, the OpName marks and the instruction index (the tile
     // prefix is already known)
@@ -1650,12 +1702,14 @@ __device__ __forceinline__ void main_body(Shared& S, const VParams& P) {
         while (ns) {
           const int p = __builtin_ctz(ns);
           ns &= ns - 1;
-          S.stage[b++] = uint32_t(lrel + p);
+          if (b < uint32_t(kNameCap)) S.names[b] = uint16_t(lrel + p);
+          ++b;
         }
       }
+      own_names = name_m;
       if (!kSem) {
         __syncthreads();
-        check_names();
+        check_names(own_names);
       }
     }
 
@@ -1673,7 +1727,7 @@ __device__ __forceinline__ void main_body(Shared& S, const VParams& P) {
         if (lane == 0) S.wref[wave] = ref;
       }
       __syncthreads();
-      if (kRes) check_names();
+      if constexpr (kRes) check_names(own_names);
       if (tid > 0) {
         uint32_t sp = S.spill[tid - 1];
         defm |= sp & 0xFu;
@@ -1698,8 +1752,20 @@ __device__ __forceinline__ void main_body(Shared& S, const VParams& P) {
           const uint32_t bm1 = bound ? bound - 1u : 0u;  // v - 1 >= bm1  <=>  v == 0 or v >= bound
           const uint32_t idm = defm | usem;
           bool oob = false;
+          if constexpr (kRes) {
+            // (the resolved walk keeps the words in LDS only)
 #pragma unroll
-          for (int p = 0; p < kLaneWords; ++p) oob |= ((idm >> p) & 1u) && (L.w[p] - 1u >= bm1);
+            for (int i = 0; i < kLaneWords / 4; ++i) {
+              const uint4 q = *reinterpret_cast<const uint4*>(&S.tw[lrel + 4 * i]);
+              oob |= ((idm >> (4 * i)) & 1u) && (q.x - 1u >= bm1);
+              oob |= ((idm >> (4 * i + 1)) & 1u) && (q.y - 1u >= bm1);
+              oob |= ((idm >> (4 * i + 2)) & 1u) && (q.z - 1u >= bm1);
+              oob |= ((idm >> (4 * i + 3)) & 1u) && (q.w - 1u >= bm1);
+            }
+          } else {
+#pragma unroll
+            for (int p = 0; p < kLaneWords; ++p) oob |= ((idm >> p) & 1u) && (L.w[p] - 1u >= bm1);
+          }
           const bool win_here = win_on && j0 == jw;
           bool dup = false;
           uint32_t dm = defm;
@@ -1778,7 +1844,7 @@ __device__ __forceinline__ void main_body(Shared& S, const VParams& P) {
     }
 
     // ---- index entries staged in LDS in tile order (slot = plain scan)
-    if (kIdx && !kRes) {
+    if constexpr (kIdx && !kRes) {
       if (!kSem) __syncthreads();  // the string checks above read stage[]
 #pragma unroll
       for (int p = 0; p < kLaneWords; ++p) {
@@ -1818,7 +1884,7 @@ __device__ __forceinline__ void main_body(Shared& S, const VParams& P) {
     const uint32_t prefix = kRes ? res_pre : S.prefix;
 
     // ---- instruction index: coalesced stores of the staged entries
-    if (kIdx && !kRes) {
+    if constexpr (kIdx && !kRes) {
       const int K = S.K;
       for (uint32_t sl = tid; sl < n_slots; sl += kBlock) {
         // modules with starts in this tile own consecutive slot ranges in
@@ -1835,6 +1901,8 @@ __device__ __forceinline__ void main_body(Shared& S, const VParams& P) {
         }
       }
     }
+
+    if constexpr (kRes) issue_prefetch();
 
     // ---- module ends owned by this lane: positions 1..16 of the window
     {
@@ -1880,9 +1948,11 @@ __device__ __forceinline__ void main_body(Shared& S, const VParams& P) {
       }
     }
     } while (false);
-    if (go_serial) {
-      if (tid == kBlock - 1) S.tnext = claim_tn;
-      serial_tile<kSem, kIdx>(S, P, t, t0, t1, serialE);
+    if constexpr (!kRes) {
+      if (go_serial) {
+        if (tid == kBlock - 1) S.tnext = claim_tn;
+        serial_tile<kSem, kIdx>(S, P, t, t0, t1, serialE);
+      }
     }
   }
   if (kSem && dc_cnt) atomicAdd(&P.mods[dc_mod].def_count, dc_cnt);
@@ -1891,8 +1961,15 @@ __device__ __forceinline__ void main_body(Shared& S, const VParams& P) {
 template <bool kSem, bool kIdx>
 __global__ __launch_bounds__(kBlock, 4) void k_main(VParams P) {
   __shared__ Shared S;
-  if (P.ctrl[kCtlMode] == kModeResolved) main_body<kSem, kIdx, true>(S, P);
-  else main_body<kSem, kIdx, false>(S, P);
+  if (P.ctrl[kCtlMode] == kModeResolved) return;  // the resolved walk ran
+  main_body<kSem, kIdx, false>(S, P);
+}
+
+template <bool kSem, bool kIdx>
+__global__ __launch_bounds__(kBlock, 5) void k_walk(VParams P) {
+  __shared__ WalkShared S;
+  if (P.ctrl[kCtlMode] != kModeResolved) return;  // the single-pass walk runs next
+  main_body<kSem, kIdx, true>(S, P);
 }
 
 // ---------------------------------------------------------------------------
@@ -2155,6 +2232,16 @@ hipError_t launch_main(const VParams& p, int grid, hipStream_t s) {
   return hipLaunchKernel(f, dim3(grid), dim3(kBlock), args, 0, s);
 }
 
+void launch_walk(const VParams& p, int grid, hipStream_t s) {
+  if (p.semantic) {
+    if (p.index) hipLaunchKernelGGL((k_walk<true, true>), dim3(grid), dim3(kBlock), 0, s, p);
+    else hipLaunchKernelGGL((k_walk<true, false>), dim3(grid), dim3(kBlock), 0, s, p);
+  } else {
+    if (p.index) hipLaunchKernelGGL((k_walk<false, true>), dim3(grid), dim3(kBlock), 0, s, p);
+    else hipLaunchKernelGGL((k_walk<false, false>), dim3(grid), dim3(kBlock), 0, s, p);
+  }
+}
+
 void launch_chain(const VParams& p, int grid, hipStream_t s) {
   hipLaunchKernelGGL(k_chain, dim3(grid), dim3(kBlock), 0, s, p);
 }
@@ -2177,6 +2264,13 @@ void launch_pass2(const VParams& p, int grid, hipStream_t s) {
 }  // namespace spv
 
 namespace spv {
+int walk_occupancy() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(k_walk<true, true>), kBlock, 0) !=
+      hipSuccess)
+    return 0;
+  return n;
+}
 int chain_occupancy() {
   int n = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(k_chain), kBlock, 0) != hipSuccess)
