@@ -98,6 +98,7 @@ int run_validate(spv_ctx* ctx, const uint32_t* words, const int64_t* mod_off, in
   p.lst = reinterpret_cast<uint32_t*>(base + L.lst);
   p.tres = reinterpret_cast<uint32_t*>(base + L.tres);
   p.rstate = reinterpret_cast<unsigned long long*>(base + L.rstate);
+  p.p2list = reinterpret_cast<uint32_t*>(base + L.p2list);
   p.semantic = semantic;
   p.index = index ? 1 : 0;
   p.sched_static = 0;

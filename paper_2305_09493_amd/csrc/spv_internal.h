@@ -73,7 +73,7 @@ static_assert(sizeof(ModState) == 48, "ModState layout");
 
 // ---- workspace layout ----------------------------------------------------
 struct Layout {
-  size_t ctrl, tileA, tileB, tfm, mods, idmap, tsum, lst, tres, rstate, total;
+  size_t ctrl, tileA, tileB, tfm, mods, idmap, tsum, lst, tres, rstate, p2list, total;
 };
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -110,12 +110,23 @@ inline Layout make_layout(int64_t n_modules, int64_t n_words) {
   off = align256(off + 8 * size_t(n_tiles + 1));
   L.rstate = off;
   off = align256(off + 8 * kStateStride * size_t(n_tiles / kResolveTiles + 2));
+  L.p2list = off;
+  off = align256(off + 4 * size_t(n_tiles + n_modules + 2));
   L.total = off;
   return L;
 }
 
 // control words (uint32) at the start of the workspace
-enum { kCtlClaim = 0, kCtlClaim2 = 1, kCtlPass2 = 2, kCtlSpinErr = 3, kCtlMode = 4, kCtlClaimR = 5, kCtlDoneR = 6 };
+enum {
+  kCtlClaim = 0,
+  kCtlClaim2 = 1,
+  kCtlPass2 = 2,
+  kCtlSpinErr = 3,
+  kCtlMode = 4,
+  kCtlClaimR = 5,
+  kCtlDoneR = 6,
+  kCtlP2Tiles = 7  // entries of the second pass's tile list
+};
 // kCtlMode: kModeResolved when the chain and resolve passes settled every
 // tile's entry and count prefix (the main pass then walks without look-back);
 // anything else selects the single-pass walk with look-back.
@@ -150,6 +161,7 @@ struct VParams {
   uint32_t* lst;    // chain-pass lane records: starts | parse-error nodes << 16
   uint32_t* tres;   // resolved tile entry and count prefix (2 words per tile)
   unsigned long long* rstate;  // resolve-pass block states (look-back)
+  uint32_t* p2list;  // tiles of the modules that need the undefined-ID pass
   int semantic;
   int index;
   // 1: tile t is processed by block t mod gridDim.x (the grid is launched

@@ -208,7 +208,10 @@ struct Shared {
   uint32_t modflags[kListMax];
   uint32_t moddef[kListMax];
   uint32_t slot0[kListMax];    // first staging slot of each module's starts in this tile
+  static constexpr int kWins = 1;     // one window: module jw
+  static constexpr int kWinW = kWinWords;
   unsigned long long win[kWinWords];  // result-ID window bitmap of module jw
+  uint32_t wmin[1];
   uint32_t nname;              // OpName starts compacted into stage[] for the string checks
   uint32_t badb[kTileWords / 32];  // tile positions whose OpName string is malformed
   LEnt cache;                  // module containing the previous tile's start
@@ -217,7 +220,7 @@ struct Shared {
 
 // Shared state of the resolved walk: no staging of index entries (they are
 // written directly), OpName starts in a short list (a tile with more checks
-// its strings lane by lane), so that six blocks fit on a CU.
+// its strings lane by lane), so that five blocks fit on a CU.
 constexpr int kNameCap = 1024;
 struct WalkShared {
   uint32_t tw[kTileWords + kTwTail] __attribute__((aligned(16)));
@@ -240,7 +243,10 @@ struct WalkShared {
   uint32_t spill[kBlock];
   uint32_t modflags[kListMax];
   uint32_t moddef[kListMax];
-  unsigned long long win[kWinWords];
+  static constexpr int kWins = 2;     // windows of list entries 0 and 1, 4096 result IDs each
+  static constexpr int kWinW = 64;
+  unsigned long long win[kWins * kWinW];
+  uint32_t wmin[kWins];               // smallest anchoring result ID of each window's module
   uint32_t nname;
   uint32_t badb[kTileWords / 32];
   LEnt cache;
@@ -885,6 +891,7 @@ __global__ __launch_bounds__(256) void k_plan(VParams P, int64_t chunk) {
     P.ctrl[kCtlMode] = 0;
     P.ctrl[kCtlClaimR] = 0;
     P.ctrl[kCtlDoneR] = 0;
+    P.ctrl[kCtlP2Tiles] = 0;
   }
   for (int64_t m = gtid; m < P.M; m += nth) {
     int64_t off = P.mod_off[m], end = P.mod_off[m + 1];
@@ -1255,8 +1262,20 @@ __device__ __forceinline__ void main_body(SH& S, const VParams& P) {
     S.tnext = (kRes || P.sched_static) ? (long long)blockIdx.x : (long long)atomicAdd(&P.ctrl[kCtlClaim], 1u);
   // result-ID window flush of the previous tile: issued at its end, its
   // returned words are examined at the start of the next tile
-  unsigned long long fl_old = 0, fl_bits = 0;
-  int64_t fl_mod = -1;
+  // (windows: SH::kWins of SH::kWinW words; thread tid flushes word
+  // k * kBlock + tid - kFlOff of slot k, whose window is aligned to its wave)
+  constexpr int kWW = SH::kWinW;
+  constexpr int kNW = SH::kWins * kWW;
+  constexpr int kSlots = (kNW + kBlock - 1) / kBlock;
+  constexpr int kFlOff = kNW < kBlock ? kBlock - kNW : 0;
+  unsigned long long fl_old[kSlots], fl_bits[kSlots];
+  int32_t fl_mk[kSlots];
+#pragma unroll
+  for (int k = 0; k < kSlots; ++k) {
+    fl_old[k] = 0;
+    fl_bits[k] = 0;
+    fl_mk[k] = -1;
+  }
   // new result IDs of the window are counted per block and added to the
   // module's count when the module changes or the block ends (one device
   // atomic per module run instead of one per tile)
@@ -1275,29 +1294,27 @@ __device__ __forceinline__ void main_body(SH& S, const VParams& P) {
     __syncthreads();
     const long long t = S.tnext;
     // fold the previous tile's flush into its module's state
-    if (kSem && fl_mod >= 0) {
-      uint32_t cnt = 0;
-      bool dup = false;
-      if (tid >= kBlock - kWinWords && fl_bits) {
-        dup = (fl_old & fl_bits) != 0;
-        cnt = uint32_t(__popcll(fl_bits & ~fl_old));
-      }
-      if (wave >= kWaves - kWinWords / 64) {
-        cnt = wave_sum_u32(cnt);
-        bool d = __ballot(dup) != 0;
-        if (lane == 0) {
-          if (cnt) {
-            if (fl_mod != dc_mod) {
-              if (dc_cnt) atomicAdd(&P.mods[dc_mod].def_count, dc_cnt);
-              dc_mod = fl_mod;
-              dc_cnt = 0;
+    if (kSem) {
+#pragma unroll
+      for (int k = 0; k < kSlots; ++k) {
+        if (fl_mk[k] >= 0) {  // the same in the whole wave
+          const bool dup = (fl_old[k] & fl_bits[k]) != 0;
+          uint32_t cnt = wave_sum_u32(uint32_t(__popcll(fl_bits[k] & ~fl_old[k])));
+          const bool d = __ballot(dup) != 0;
+          if (lane == 0) {
+            if (cnt) {
+              if (fl_mk[k] != dc_mod) {
+                if (dc_cnt) atomicAdd(&P.mods[dc_mod].def_count, dc_cnt);
+                dc_mod = fl_mk[k];
+                dc_cnt = 0;
+              }
+              dc_cnt += cnt;
             }
-            dc_cnt += cnt;
+            if (d) atomicOr(&P.mods[fl_mk[k]].flags, kModDup);
           }
-          if (d) atomicOr(&P.mods[fl_mod].flags, kModDup);
         }
+        fl_mk[k] = -1;
       }
-      fl_mod = -1;
     }
     if (t >= P.n_tiles) break;
     const int64_t t0 = t * kTileWords;
@@ -1344,7 +1361,10 @@ __device__ __forceinline__ void main_body(SH& S, const VParams& P) {
       S.moddef[tid] = 0;
       if constexpr (!kRes) S.slot0[tid] = 0xFFFFFFFFu;
     }
-    if (kSem && tid < kWinWords) S.win[tid] = 0;
+    if (kSem) {
+      for (int i = tid; i < kNW; i += kBlock) S.win[i] = 0;
+      if (tid < SH::kWins) S.wmin[tid] = 0xFFFFFFFFu;
+    }
     if (tid < kTileWords / 32) S.badb[tid] = 0;
     if (tid == 0) {
       S.serial = 0;
@@ -1666,6 +1686,16 @@ __device__ __forceinline__ void main_body(SH& S, const VParams& P) {
       uint32_t name_m = 0;
       uint32_t sm = starts;
       uint32_t k = 0;
+      // lanes inside one module: index entries at dst0 + k, values val0 + p
+      int64_t dst0 = 0;
+      uint32_t val0 = 0;
+      bool ok0 = false;
+      if (kIdx && rst == 0) {
+        const LEnt& le = S.list[L.j0];
+        ok0 = (le.info & kInfoHdrOk) != 0;
+        dst0 = le.off + pre_local + (lane_in_first ? res_pre : 0u);
+        val0 = uint32_t(t0 + lrel - le.off);
+      }
       while (sm) {
         const int p = __builtin_ctz(sm);
         sm &= sm - 1;
@@ -1677,20 +1707,19 @@ __device__ __forceinline__ void main_body(SH& S, const VParams& P) {
           usem |= (ee >> 28) << (p + 1);
         }
         if (kIdx) {
-          int jm;
-          uint32_t rank;
           if (rst == 0) {
-            jm = L.j0;
-            rank = pre_local + k + (lane_in_first ? res_pre : 0u);
+            if (ok0) {
+              P.idx_off[dst0 + k] = val0 + uint32_t(p);
+              P.idx_op[dst0 + k] = uint16_t(w0 & 0xFFFFu);
+            }
           } else {
-            jm = lane_mod_at(L, p);
-            rank = rank_local(p) + (in_first(p) ? res_pre : 0u);
-          }
-          const LEnt& le = S.list[jm];
-          if (le.info & kInfoHdrOk) {
-            const int64_t dst = le.off + rank;
-            P.idx_off[dst] = uint32_t(t0 + lrel + p - le.off);
-            P.idx_op[dst] = uint16_t(w0 & 0xFFFFu);
+            const int jm = lane_mod_at(L, p);
+            const LEnt& le = S.list[jm];
+            if (le.info & kInfoHdrOk) {
+              const int64_t dst = le.off + rank_local(p) + (in_first(p) ? res_pre : 0u);
+              P.idx_off[dst] = uint32_t(t0 + lrel + p - le.off);
+              P.idx_op[dst] = uint16_t(w0 & 0xFFFFu);
+            }
           }
         }
         ++k;
@@ -1715,16 +1744,28 @@ __device__ __forceinline__ void main_body(SH& S, const VParams& P) {
 
     // ---- result-ID checks
     if (kSem) {
-      // LDS window for the result IDs of module jw in this tile: anchored at
-      // the first result ID found by the lowest wave that has one
+      // LDS windows for the result IDs of this tile.  One window: module jw,
+      // anchored at the first result ID found by the lowest wave that has
+      // one.  Several: list entries 0.., each anchored at the smallest first
+      // result ID of its lanes.
       const int jw = S.jw;
-      {
+      // a tile inside one module has one window over the whole window space
+      const bool one = SH::kWins == 1 || S.K == 1;
+      if (one) {
         const uint32_t dw = (L.rst == 0 && L.j0 == jw) ? (defm & 0xFFFFu) : 0u;
         const uint32_t first = dw ? S.tw[lrel + __builtin_ctz(dw)] : 0u;
         uint64_t bal = __ballot(dw != 0);
         uint32_t ref = 0xFFFFFFFFu;
         if (bal) ref = __shfl(first, int(__builtin_ctzll(bal)));
         if (lane == 0) S.wref[wave] = ref;
+      } else {
+        const uint32_t dw = defm & 0xFFFFu;
+        if (L.rst == 0 && L.j0 < SH::kWins && dw) {
+          const LEnt& le = S.list[L.j0];
+          const uint32_t v = S.tw[lrel + __builtin_ctz(dw)];
+          if (le.mod >= 0 && (le.info & kInfoHdrOk) && !(le.info & kInfoSparse) && v != 0u && v < le.bound)
+            atomicMin(&S.wmin[L.j0], v);
+        }
       }
       __syncthreads();
       if constexpr (kRes) check_names(own_names);
@@ -1735,11 +1776,26 @@ __device__ __forceinline__ void main_body(SH& S, const VParams& P) {
       }
       defm &= 0xFFFFu;
       usem &= 0xFFFFu;
-      uint32_t ref = 0xFFFFFFFFu;
-      for (int w = kWaves - 1; w >= 0; --w)
-        if (S.wref[w] != 0xFFFFFFFFu) ref = S.wref[w];
-      const bool win_on = jw >= 0 && ref != 0xFFFFFFFFu;
-      const uint32_t base64 = (ref > 2048u ? ref - 2048u : 0u) & ~63u;
+      uint32_t ref1 = 0xFFFFFFFFu;
+      if (one) {
+        for (int w = kWaves - 1; w >= 0; --w)
+          if (S.wref[w] != 0xFFFFFFFFu) ref1 = S.wref[w];
+      }
+      // words of a window, window of list entry j (-1: none), its base
+      const uint32_t wsz = one ? uint32_t(kNW) : uint32_t(kWW);
+      auto win_of = [&](int j) -> int {
+        if (one) return (jw >= 0 && ref1 != 0xFFFFFFFFu && j == jw) ? 0 : -1;
+        return (j < SH::kWins && S.wmin[j] != 0xFFFFFFFFu) ? j : -1;
+      };
+      auto win_base = [&](int w) -> uint32_t {
+        const uint32_t r = one ? ref1 : S.wmin[w];
+        return (r > 16u * wsz ? r - 16u * wsz : 0u) & ~63u;  // a quarter of the window below the anchor
+      };
+      // set result ID v in window w (v inside it); true if it was set before
+      auto win_set = [&](int w, uint32_t base, uint32_t v) -> bool {
+        const unsigned long long bit = 1ull << (v & 63u);
+        return (atomicOr(&S.win[w * wsz + ((v - base) >> 6)], bit) & bit) != 0;
+      };
       // Lanes inside one bitmap-mode module: bound check of every ID word,
       // LDS-window insertion of the result IDs.  Every other ID word (result
       // outside the window, hash-mode module, lanes with a module start) is
@@ -1766,7 +1822,8 @@ __device__ __forceinline__ void main_body(SH& S, const VParams& P) {
 #pragma unroll
             for (int p = 0; p < kLaneWords; ++p) oob |= ((idm >> p) & 1u) && (L.w[p] - 1u >= bm1);
           }
-          const bool win_here = win_on && j0 == jw;
+          const int wj = win_of(j0);
+          const uint32_t base = wj >= 0 ? win_base(wj) : 0u;
           bool dup = false;
           uint32_t dm = defm;
           while (dm) {
@@ -1774,10 +1831,8 @@ __device__ __forceinline__ void main_body(SH& S, const VParams& P) {
             dm &= dm - 1;
             const uint32_t v = S.tw[lrel + p];
             if (v - 1u >= bm1) continue;  // out of bound: flagged above
-            if (win_here && v >= base64 && v - base64 < 64u * kWinWords) {
-              const unsigned long long bit = 1ull << (v & 63u);
-              const unsigned long long old = atomicOr(&S.win[(v - base64) >> 6], bit);
-              dup |= (old & bit) != 0;
+            if (wj >= 0 && v >= base && v - base < 64u * wsz) {
+              dup |= win_set(wj, base, v);
             } else {
               rare |= 1u << p;
             }
@@ -1797,11 +1852,10 @@ __device__ __forceinline__ void main_body(SH& S, const VParams& P) {
         if (!(le.info & kInfoHdrOk)) continue;
         uint32_t v = S.tw[lrel + p];
         bool is_def = (defm >> p) & 1u;
-        if (win_on && is_def && jm == jw && v != 0u && v < le.bound && v >= base64 &&
-            v - base64 < 64u * kWinWords) {
-          unsigned long long bit = 1ull << (v & 63u);
-          unsigned long long old = atomicOr(&S.win[(v - base64) >> 6], bit);
-          if (old & bit) atomicOr(&S.modflags[jm], kModDup);
+        const int wj = win_of(jm);
+        const uint32_t base = wj >= 0 ? win_base(wj) : 0u;
+        if (wj >= 0 && is_def && v != 0u && v < le.bound && v >= base && v - base < 64u * wsz) {
+          if (win_set(wj, base, v)) atomicOr(&S.modflags[jm], kModDup);
         } else {
           id_check(P, le, v, is_def, &S.modflags[jm], &S.moddef[jm]);
         }
@@ -1817,10 +1871,10 @@ __device__ __forceinline__ void main_body(SH& S, const VParams& P) {
           const LEnt& le = S.list[jm];
           if (!(le.info & kInfoHdrOk)) continue;
           const uint32_t v = S.tw[kTileWords + k];
-          if (d && win_on && jm == jw && v != 0u && v < le.bound && v >= base64 && v - base64 < 64u * kWinWords) {
-            unsigned long long bit = 1ull << (v & 63u);
-            unsigned long long old = atomicOr(&S.win[(v - base64) >> 6], bit);
-            if (old & bit) atomicOr(&S.modflags[jm], kModDup);
+          const int wj = win_of(jm);
+          const uint32_t base = wj >= 0 ? win_base(wj) : 0u;
+          if (d && wj >= 0 && v != 0u && v < le.bound && v >= base && v - base < 64u * wsz) {
+            if (win_set(wj, base, v)) atomicOr(&S.modflags[jm], kModDup);
           } else {
             id_check(P, le, v, d, &S.modflags[jm], &S.moddef[jm]);
           }
@@ -1830,11 +1884,23 @@ __device__ __forceinline__ void main_body(SH& S, const VParams& P) {
       // window flush: one device atomic per 64 result IDs, issued by the last
       // waves (wave 0 polls other tiles' states next); the returned words are
       // examined at the start of the next tile
-      fl_mod = win_on ? int64_t(S.list[jw].mod) : -1;
-      if (win_on && tid >= kBlock - kWinWords) {
-        const int i = tid - (kBlock - kWinWords);
-        fl_bits = S.win[i];
-        fl_old = fl_bits ? atomicOr(&P.idmap[S.list[jw].off + (base64 >> 6) + i], fl_bits) : 0ull;
+#pragma unroll
+      for (int k = 0; k < kSlots; ++k) {
+        const int i = k * kBlock + tid - kFlOff;
+        fl_mk[k] = -1;
+        fl_bits[k] = 0;
+        fl_old[k] = 0;
+        if (i >= 0 && i < kNW) {
+          const int w = one ? 0 : i / kWW;
+          const int jl = one ? jw : w;
+          if (win_of(jl) >= 0) {
+            const LEnt& le = S.list[jl];
+            fl_mk[k] = le.mod;
+            fl_bits[k] = S.win[i];
+            if (fl_bits[k])
+              fl_old[k] = atomicOr(&P.idmap[le.off + (win_base(w) >> 6) + (i - w * int(wsz))], fl_bits[k]);
+          }
+        }
       }
       if (tid < S.K && S.list[tid].mod >= 0) {
         ModState& ms = P.mods[S.list[tid].mod];
@@ -1988,6 +2054,13 @@ __global__ __launch_bounds__(256) void k_finalize(VParams P, int phase) {
         if (need) {
           ms.flags |= kModPass2;
           atomicAdd(&P.ctrl[kCtlPass2], 1u);
+          // the module's tiles join the second pass's list
+          const int64_t off = P.mod_off[m], end = P.mod_off[m + 1];
+          if (end > off) {
+            const int64_t a = off / kTileWords, b = (end - 1) / kTileWords;
+            const uint32_t base = atomicAdd(&P.ctrl[kCtlP2Tiles], uint32_t(b - a + 1));
+            for (int64_t i = 0; i <= b - a; ++i) P.p2list[base + i] = uint32_t(a + i);
+          }
         }
       }
       continue;
@@ -2025,11 +2098,12 @@ __global__ __launch_bounds__(kBlock) void k_pass2(VParams P) {
   const int tid = threadIdx.x;
   const int wave = tid >> 6;
   const int lane = tid & 63;
-  for (;;) {
-    if (tid == 0) S.t = atomicAdd(&P.ctrl[kCtlClaim2], 1u);
-    __syncthreads();
-    const long long t = S.t;
-    if (t >= P.n_tiles) break;
+  // tiles of the marked modules, listed by the first finalize phase, in
+  // block order (a tile of two marked modules may come twice: the checks
+  // only set flags)
+  const long long n_list = P.ctrl[kCtlP2Tiles];
+  for (long long li = blockIdx.x; li < n_list; li += gridDim.x) {
+    const long long t = P.p2list[li];
     const int64_t t0 = t * kTileWords;
     const int64_t t1 = (t0 + kTileWords < P.W) ? t0 + kTileWords : P.W;
     if (wave == 0) build_list(S, P, t, t0, t1);
