@@ -109,8 +109,10 @@ int spv_destroy(spv_ctx *ctx);
 const char *spv_last_hip_error(spv_ctx *ctx);
 
 /* Launch tuning (0 = keep the built-in default).  blocks_per_cu sets the
- * persistent grid of the decode/validate kernel; encode_block sets the
- * records per encode block (a multiple of 256). */
+ * persistent grid of the single-pass decode/validate walk (a value above the
+ * kernel's resident blocks per CU also turns off its cooperative, static tile
+ * order); encode_block sets the records per encode block (a multiple of 256,
+ * at most 4096; SPV_ERR_INVALID_ARG otherwise). */
 int spv_set_tuning(spv_ctx *ctx, int blocks_per_cu, int encode_block);
 /* Current launch tuning of the context. */
 int spv_get_tuning(spv_ctx *ctx, int *blocks_per_cu, int *encode_block);

@@ -246,7 +246,8 @@ int spv_read_timing(spv_ctx* ctx, double* total_ms, int64_t* n_launches) {
 const char* spv_last_hip_error(spv_ctx* ctx) { return ctx ? ctx->msg : "no context"; }
 
 int spv_set_tuning(spv_ctx* ctx, int blocks_per_cu, int encode_block) {
-  if (!ctx || blocks_per_cu < 0 || encode_block < 0 || (encode_block % 256) != 0) return SPV_ERR_INVALID_ARG;
+  if (!ctx || blocks_per_cu < 0 || encode_block < 0 || (encode_block % 256) != 0 || encode_block > 4096)
+    return SPV_ERR_INVALID_ARG;
   if (blocks_per_cu > 0) ctx->blocks_per_cu = blocks_per_cu;
   if (encode_block > 0) ctx->encode_block = encode_block;
   return SPV_SUCCESS;
@@ -329,6 +330,9 @@ int spv_encode(spv_ctx* ctx, const uint16_t* op, const int32_t* opnd_off, const 
   p.enc_bad = enc_bad_record;
   p.ctrl = reinterpret_cast<uint32_t*>(base + L.ctrl);
   p.blk = reinterpret_cast<unsigned long long*>(base + L.blk);
+  p.blkx = reinterpret_cast<unsigned long long*>(base + L.blkx);
+  p.sstate = reinterpret_cast<unsigned long long*>(base + L.sstate);
+  p.bmod = reinterpret_cast<int64_t*>(base + L.bmod);
   p.mod_bad = reinterpret_cast<unsigned long long*>(base + L.mod_bad);
   p.mod_maxid = reinterpret_cast<uint32_t*>(base + L.mod_maxid);
   p.mod_words = reinterpret_cast<int64_t*>(base + L.mod_words);

@@ -9,10 +9,14 @@
 //
 // How: record r's output position is 5 * (m + 1) + S(r), where m is its
 // module and S(r) the sum of the word counts of all records before r - a
-// plain exclusive scan, computed in one pass with a decoupled look-back over
-// blocks of records, followed by the scatter in the same pass.  Module
-// failures (rare) are found in the same pass; a module that fails writes no
-// words, so when any module fails a compaction kernel closes the gaps.
+// plain exclusive scan.  Three passes with no waiting between blocks: word
+// totals per block of records, a scan of those totals (blocks of 256
+// totals chained by a decoupled look-back), and the scatter, in which every
+// block re-derives its records' word counts and positions.  Records are
+// handed to threads in slices of 256 consecutive records, so every load of a
+// record field is coalesced.  Module failures (rare) are found in the
+// scatter; a module that fails writes no words, so when any module fails a
+// compaction kernel closes the gaps.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -67,13 +71,8 @@ __device__ __forceinline__ void st_state_e(unsigned long long* p, unsigned long 
 }
 
 constexpr unsigned long long kEAgg = 1ull << 62, kEIncl = 2ull << 62, kEMask = 3ull << 62;
+constexpr int kEStateStride = 16;  // one 128-byte line per scan-block state
 constexpr unsigned long long kESum = (1ull << 62) - 1;
-
-// module of record r, searching forward from a module known to start at or before r
-__device__ __forceinline__ int64_t module_of(const int64_t* rec_mod_off, int64_t M, int64_t m, int64_t r) {
-  while (m + 1 < M && rec_mod_off[m + 1] <= r) ++m;
-  return m;
-}
 
 }  // namespace
 
@@ -84,171 +83,321 @@ __global__ __launch_bounds__(256) void k_enc_init(EParams P) {
     P.ctrl[0] = 0;
     P.ctrl[1] = 0;
     P.ctrl[2] = 0;
+    P.ctrl[3] = 0;
   }
-  for (int64_t i = gtid; i < P.n_blocks; i += nth) P.blk[i] = 0;
+  for (int64_t i = gtid; i < P.n_blocks / kEncThreads + 2; i += nth) P.sstate[i * kEStateStride] = 0;
   for (int64_t m = gtid; m < P.M; m += nth) {
     P.mod_bad[m] = ~0ull;
     P.mod_maxid[m] = 0;
     P.mod_words[m] = -1;
   }
+  // module of each block's first record: the last m with rec_mod_off[m] <= r0
+  // (the non-empty module holding r0); all blocks search at once
+  for (int64_t b = gtid; b < P.n_blocks; b += nth) {
+    const int64_t r0 = b * P.block_records;
+    int64_t lo = 0, hi = P.M - 1;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) >> 1;
+      if (P.rec_mod_off[mid] <= r0) lo = mid;
+      else hi = mid - 1;
+    }
+    P.bmod[b] = lo;
+  }
 }
 
-// One pass: per-record word counts and checks, exclusive scan with look-back,
-// scatter of every record's words.
-__global__ __launch_bounds__(kEncThreads) void k_enc_main(EParams P) {
-  __shared__ uint16_t tbl[257];
-  __shared__ long long s_b;
-  __shared__ unsigned long long s_wsum[kEncThreads / 64];
-  __shared__ unsigned long long s_prefix;
-  __shared__ long long s_m0;
-  enc_table(tbl);
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
-  const int rpt = P.block_records / kEncThreads;
+constexpr int kEncMaxSlices = 16;  // records per thread of a block (block_records / 256)
 
-  for (;;) {
-    if (tid == 0) s_b = atomicAdd(&P.ctrl[0], 1u);
-    __syncthreads();
-    const long long b = s_b;
-    if (b >= P.n_blocks) break;
+// Word count of record r (first word + operand words + string words).
+__device__ __forceinline__ uint32_t enc_wc(const EParams& P, const uint16_t* tbl, int64_t r) {
+  const uint32_t op = P.op[r];
+  const int64_t n_ops = int64_t(P.opnd_off[r + 1]) - P.opnd_off[r];
+  const int64_t L = int64_t(P.str_off[r + 1]) - P.str_off[r];
+  const uint32_t e = tbl[op < 256u ? op : 256u];
+  const bool name = (e >> 8) & 1u;
+  return uint32_t(1 + n_ops + ((name || L > 0) ? L / 4 + 1 : 0));
+}
+
+__device__ __forceinline__ uint32_t enc_wave_incl(uint32_t x) {
+  const int lane = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t u = __shfl_up(x, d);
+    if (lane >= d) x += u;
+  }
+  return x;
+}
+
+// Pass 1: word total of each block of records.
+__global__ __launch_bounds__(kEncThreads) void k_enc_count(EParams P) {
+  __shared__ uint16_t tbl[257];
+  __shared__ unsigned long long s_w[kEncThreads / 64];
+  enc_table(tbl);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int rpt = P.block_records / kEncThreads;
+  for (long long b = blockIdx.x; b < P.n_blocks; b += gridDim.x) {
     const int64_t r0 = b * P.block_records;
-    const int64_t r1 = (r0 + P.block_records < P.N) ? r0 + P.block_records : P.N;
+    unsigned long long sum = 0;
+#pragma unroll
+    for (int k = 0; k < kEncMaxSlices; ++k) {
+      const int64_t r = r0 + int64_t(k) * kEncThreads + tid;
+      if (k < rpt && r < P.N) sum += enc_wc(P, tbl, r);
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) sum += __shfl_xor(sum, d);
+    if (lane == 0) s_w[wave] = sum;
+    __syncthreads();
     if (tid == 0) {
-      // module of r0: last m with rec_mod_off[m] <= r0
-      int64_t lo = 0, hi = P.M - 1;
-      while (lo < hi) {
-        int64_t mid = (lo + hi + 1) >> 1;
-        if (P.rec_mod_off[mid] <= r0) lo = mid;
-        else hi = mid - 1;
-      }
-      s_m0 = lo;
+      unsigned long long tot = 0;
+      for (int w = 0; w < kEncThreads / 64; ++w) tot += s_w[w];
+      P.blk[b] = tot;
     }
     __syncthreads();
-    const int64_t rb = r0 + int64_t(tid) * rpt;
-    // pass 1 over this thread's records: word counts
-    unsigned long long mysum = 0;
-    for (int k = 0; k < rpt; ++k) {
-      int64_t r = rb + k;
-      if (r >= r1) break;
-      uint32_t op = P.op[r];
-      int64_t n_ops = int64_t(P.opnd_off[r + 1]) - P.opnd_off[r];
-      int64_t L = int64_t(P.str_off[r + 1]) - P.str_off[r];
-      uint32_t e = tbl[op < 256u ? op : 256u];
-      bool name = (e >> 8) & 1u;
-      mysum += uint64_t(1 + n_ops + ((name || L > 0) ? L / 4 + 1 : 0));
-    }
-    // block exclusive scan of the thread sums
-    unsigned long long inc = mysum;
+  }
+}
+
+// Pass 2: exclusive scan of the block totals into blkx (blocks of 256 totals,
+// claimed in order, chained by a decoupled look-back); blkx[n_blocks] is the
+// grand total.
+__global__ __launch_bounds__(kEncThreads) void k_enc_scan(EParams P) {
+  __shared__ uint32_t s_bid;
+  __shared__ unsigned long long s_w[kEncThreads / 64];
+  __shared__ unsigned long long s_pre;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid == 0) s_bid = atomicAdd(&P.ctrl[3], 1u);
+  __syncthreads();
+  const long long sb = s_bid;
+  const long long i = sb * kEncThreads + tid;
+  const unsigned long long v = (i < P.n_blocks) ? P.blk[i] : 0ull;
+  unsigned long long inc = v;
 #pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      unsigned long long u = __shfl_up(inc, d);
-      if (lane >= d) inc += u;
+  for (int d = 1; d < 64; d <<= 1) {
+    const unsigned long long u = __shfl_up(inc, d);
+    if (lane >= d) inc += u;
+  }
+  if (lane == 63) s_w[wave] = inc;
+  __syncthreads();
+  unsigned long long wpre = 0, tot = 0;
+  for (int w = 0; w < kEncThreads / 64; ++w) {
+    if (w < wave) wpre += s_w[w];
+    tot += s_w[w];
+  }
+  if (tid == 64) st_state_e(&P.sstate[sb * kEStateStride], kEAgg | tot);
+  if (wave == 0) {
+    unsigned long long prefix = 0;
+    long long hi = sb - 1;
+    uint32_t spins = 0;
+    while (hi >= 0) {
+      const long long u = hi - lane;
+      const unsigned long long st = (u >= 0) ? ld_state_e(&P.sstate[u * kEStateStride]) : kEIncl;
+      const unsigned long long f = st & kEMask;
+      const uint64_t stopm = __ballot(f == kEIncl);
+      const uint64_t unpub = __ballot(f == 0);
+      const int sl = stopm ? int(__builtin_ctzll(stopm)) : 64;
+      const uint64_t need = (sl >= 63) ? ~0ull : ((2ull << sl) - 1ull);
+      if (unpub & need) {
+        if (++spins > kSpinLimit) {
+          if (lane == 0) atomicOr(&P.ctrl[2], 1u);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        continue;
+      }
+      unsigned long long c = (lane <= sl) ? (st & kESum) : 0ull;
+#pragma unroll
+      for (int d = 32; d >= 1; d >>= 1) c += __shfl_xor(c, d);
+      prefix += c;
+      if (sl < 64) break;
+      hi -= 64;
     }
-    if (lane == 63) s_wsum[wave] = inc;
+    if (lane == 0) {
+      st_state_e(&P.sstate[sb * kEStateStride], kEIncl | (prefix + tot));
+      s_pre = prefix;
+    }
+  }
+  __syncthreads();
+  const unsigned long long ex = s_pre + wpre + (inc - v);
+  if (i <= P.n_blocks) P.blkx[i] = ex;  // (blkx[n_blocks]: the grand total)
+}
+
+// Pass 3: checks and scatter.  kEncChunk slices of 256 records per step:
+// the fields and operands of all of a thread's records of the step are loaded
+// before any is used, and one block scan gives all their positions.  One
+// slice per step measured fastest (more slices cost occupancy).
+constexpr int kEncChunk = 1;
+
+__global__ __launch_bounds__(kEncThreads) void k_enc_scatter(EParams P) {
+  __shared__ uint16_t tbl[257];
+  __shared__ uint32_t s_w[kEncChunk][kEncThreads / 64];
+  __shared__ int64_t s_off[kEncThreads + 1];  // rec_mod_off[m0 .. m0 + 256], past M: no start
+  enc_table(tbl);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int rpt = P.block_records / kEncThreads;
+  const uint16_t* __restrict__ opc = P.op;
+  const int32_t* __restrict__ ooff = P.opnd_off;
+  const uint32_t* __restrict__ opnd = P.opnd;
+  const int32_t* __restrict__ soff = P.str_off;
+  uint32_t* __restrict__ out = P.words_out;
+  for (long long b = blockIdx.x; b < P.n_blocks; b += gridDim.x) {
+    const int64_t r0 = b * P.block_records;
+    unsigned long long base_s = P.blkx[b];  // words of all records before this block
+    const int64_t m0 = P.bmod[b];
+    // starts of the modules from m0 on, so that finding a record's module
+    // costs LDS reads; beyond the staged range the offsets are read from HBM
+    __syncthreads();  // the previous block's reads of s_off are done
+    s_off[tid] = (m0 + tid <= P.M) ? P.rec_mod_off[m0 + tid] : INT64_MAX;
+    if (tid == 0) s_off[kEncThreads] = (m0 + kEncThreads <= P.M) ? P.rec_mod_off[m0 + kEncThreads] : INT64_MAX;
     __syncthreads();
-    unsigned long long wpre = 0, tot = 0;
-    for (int w = 0; w < kEncThreads / 64; ++w) {
-      if (w < wave) wpre += s_wsum[w];
-      tot += s_wsum[w];
-    }
-    if (wave == 0) {
-      // look-back over 64 predecessor blocks per round trip
-      if (lane == 0) st_state_e(&P.blk[b], kEAgg | tot);
-      unsigned long long prefix = 0;
-      long long hi = b - 1;
-      uint32_t spins = 0;
-      while (hi >= 0) {
-        long long u = hi - lane;
-        unsigned long long st = (u >= 0) ? ld_state_e(&P.blk[u]) : kEIncl;
-        unsigned long long f = st & kEMask;
-        uint64_t stopm = __ballot(f == kEIncl);
-        uint64_t unpub = __ballot(f == 0);
-        int sl = stopm ? int(__builtin_ctzll(stopm)) : 64;
-        uint64_t need = (sl >= 63) ? ~0ull : ((2ull << sl) - 1ull);
-        if (unpub & need) {
-          if (++spins > kSpinLimit) {
-            if (lane == 0) atomicOr(&P.ctrl[2], 1u);
-            break;
+    auto off_at = [&](int64_t i) -> int64_t {  // rec_mod_off[m0 + i]
+      return (i >= 0 && i <= kEncThreads) ? s_off[i] : P.rec_mod_off[m0 + i];
+    };
+    int64_t ml = 0;  // this thread's current module, relative to m0
+    for (int k0 = 0; k0 < rpt; k0 += kEncChunk) {
+      int64_t r[kEncChunk], o0[kEncChunk], n_ops[kEncChunk], s0[kEncChunk], L[kEncChunk];
+      uint32_t op[kEncChunk], wc[kEncChunk], e[kEncChunk];
+      bool real[kEncChunk];
+#pragma unroll
+      for (int j = 0; j < kEncChunk; ++j) {
+        r[j] = r0 + int64_t(k0 + j) * kEncThreads + tid;
+        real[j] = (k0 + j < rpt) && r[j] < P.N;
+        op[j] = real[j] ? opc[r[j]] : 0u;
+        o0[j] = real[j] ? ooff[r[j]] : 0;
+        n_ops[j] = real[j] ? int64_t(ooff[r[j] + 1]) - o0[j] : 0;
+        s0[j] = real[j] ? soff[r[j]] : 0;
+        L[j] = real[j] ? int64_t(soff[r[j] + 1]) - s0[j] : 0;
+      }
+      // operands of the common counts, loaded before anything is written
+      uint32_t v[kEncChunk][4];
+#pragma unroll
+      for (int j = 0; j < kEncChunk; ++j)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[j][i] = (i < n_ops[j] && n_ops[j] <= 4) ? opnd[o0[j] + i] : 0u;
+      uint32_t winc[kEncChunk];
+#pragma unroll
+      for (int j = 0; j < kEncChunk; ++j) {
+        e[j] = tbl[op[j] < 256u ? op[j] : 256u];
+        const bool name = (e[j] >> 8) & 1u;
+        const int64_t sw = (name || L[j] > 0) ? L[j] / 4 + 1 : 0;
+        wc[j] = real[j] ? uint32_t(1 + n_ops[j] + sw) : 0u;
+        winc[j] = enc_wave_incl(wc[j]);
+        if (lane == 63) s_w[j][wave] = winc[j];
+      }
+      __syncthreads();
+      unsigned long long S[kEncChunk];
+      {
+        unsigned long long run = base_s;
+#pragma unroll
+        for (int j = 0; j < kEncChunk; ++j) {
+          uint32_t wpre = 0, stot = 0;
+#pragma unroll
+          for (int w = 0; w < kEncThreads / 64; ++w) {
+            if (w < wave) wpre += s_w[j][w];
+            stot += s_w[j][w];
           }
-          __builtin_amdgcn_s_sleep(1);
-          continue;
+          S[j] = run + wpre + (winc[j] - wc[j]);
+          run += stot;
         }
-        unsigned long long c = (lane <= sl) ? (st & kESum) : 0ull;
+        base_s = run;
+      }
+      __syncthreads();
+      uint32_t maxid = 0;
+      int64_t max_m = -1;
 #pragma unroll
-        for (int d = 32; d >= 1; d >>= 1) c += __shfl_xor(c, d);
-        prefix += c;
-        if (sl < 64) break;
-        hi -= 64;
+      for (int j = 0; j < kEncChunk; ++j) {
+        if (!real[j]) continue;
+        // module of r (forward from the block's first module)
+        while (m0 + ml + 1 < P.M && off_at(ml + 1) <= r[j]) ++ml;
+        const int64_t mr = m0 + ml;
+        if (r[j] == off_at(ml)) {
+          // first record of module mr (and of the empty modules just before it)
+          for (int64_t mm = ml; m0 + mm >= 0 && off_at(mm) == r[j]; --mm) P.mod_words[m0 + mm] = int64_t(S[j]);
+        }
+        if (mr != max_m) {
+          if (maxid) atomicMax(&P.mod_maxid[max_m], maxid);
+          maxid = 0;
+          max_m = mr;
+        }
+        const bool known = (e[j] & 0x8000u) != 0;
+        const bool name = (e[j] >> 8) & 1u;
+        const uint32_t idm = (e[j] >> 4) & 0xFu;
+        const int64_t sw = (name || L[j] > 0) ? L[j] / 4 + 1 : 0;
+        uint32_t code = 0;
+        if (!known) code = SPV_ENC_UNKNOWN_OPCODE;
+        else if (n_ops[j] != int64_t(e[j] & 0xFu)) code = SPV_ENC_OPERAND_COUNT;
+        else if (!name && L[j] > 0) code = SPV_ENC_BAD_STRING;
+        bool bad_id = false, nul = false;
+        const int64_t base = 5 * (mr + 1) + int64_t(S[j]);
+        const bool fits = base + 1 + n_ops[j] + sw <= P.words_cap;
+        if (fits) out[base] = uint32_t(((1 + n_ops[j] + sw) & 0xFFFF) << 16) | (op[j] & 0xFFFFu);
+        if (n_ops[j] <= 4) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            if (i < n_ops[j]) {
+              if ((idm >> i) & 1u) {
+                if (v[j][i] == 0xFFFFFFFFu) bad_id = true;
+                else if (v[j][i] + 1u > maxid) maxid = v[j][i] + 1u;
+              }
+              if (fits) out[base + 1 + i] = v[j][i];
+            }
+          }
+        } else {
+          for (int64_t i = 0; i < n_ops[j]; ++i) {
+            const uint32_t x = opnd[o0[j] + i];
+            if (i < 4 && ((idm >> i) & 1u)) {
+              if (x == 0xFFFFFFFFu) bad_id = true;
+              else if (x + 1u > maxid) maxid = x + 1u;
+            }
+            if (fits) out[base + 1 + i] = x;
+          }
+        }
+        // string words: little-endian packing of the characters, NUL padded;
+        // a NUL among the characters is a bad string.  The characters are read
+        // as aligned 32-bit words (an aligned word never crosses a page, so
+        // the bytes around the string that share its first and last words are
+        // safe to read), eight output words at a time, all loads issued before
+        // use, and realigned with a byte funnel shift.
+        if (sw > 0) {
+          const uint32_t* cw = reinterpret_cast<const uint32_t*>(reinterpret_cast<uintptr_t>(P.chars + s0[j]) & ~uintptr_t(3));
+          const uint32_t sh = uint32_t(reinterpret_cast<uintptr_t>(P.chars + s0[j]) & 3u);
+          for (int64_t s8 = 0; s8 < sw; s8 += 8) {
+            const int64_t need = (L[j] - 4 * s8 + int64_t(sh) + 3) / 4;  // aligned words holding characters
+            uint32_t a[9];
+#pragma unroll
+            for (int q = 0; q < 9; ++q) a[q] = (q < need) ? cw[s8 + q] : 0u;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+              if (s8 + q < sw) {
+                uint32_t word = __builtin_amdgcn_alignbyte(a[q + 1], a[q], sh);
+                const int64_t rem = L[j] - 4 * (s8 + q);  // characters left in this word
+                const uint32_t keep = rem >= 4 ? 0xFFFFFFFFu : (rem <= 0 ? 0u : ((1u << (8 * rem)) - 1u));
+                word &= keep;
+                const uint32_t probe = word | ~keep;  // positions past the string never read as NUL
+                nul |= ((probe - 0x01010101u) & ~probe & 0x80808080u) != 0;
+                if (fits) out[base + 1 + n_ops[j] + s8 + q] = word;
+              }
+            }
+          }
+        }
+        // checks in the order of the record contract: grammar, string, length, IDs
+        if (code == 0 && nul) code = SPV_ENC_BAD_STRING;
+        if (code == 0 && 1 + n_ops[j] + sw > 65535) code = SPV_ENC_TOO_LONG;
+        if (code == 0 && bad_id) code = SPV_ENC_BAD_ID;
+        if (code) atomicMin(&P.mod_bad[mr], ((unsigned long long)(r[j] - P.rec_mod_off[mr]) << 8) | code);
       }
-      if (lane == 0) {
-        st_state_e(&P.blk[b], kEIncl | (prefix + tot));
-        s_prefix = prefix;
+      // bound: max ID + 1 per module (one atomic per wave when the wave's
+      // records of this chunk are in one module)
+      const int64_t mlead = __shfl(max_m, 0);
+      if (__ballot(max_m != mlead) == 0 && mlead >= 0) {
+        uint32_t mx = maxid;
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) {
+          const uint32_t o = __shfl_xor(mx, d);
+          mx = o > mx ? o : mx;
+        }
+        if (lane == 0 && mx) atomicMax(&P.mod_maxid[mlead], mx);
+      } else if (maxid) {
+        atomicMax(&P.mod_maxid[max_m], maxid);
       }
     }
-    __syncthreads();
-    unsigned long long S = s_prefix + wpre + (inc - mysum);  // words of all records before rb
-    // pass 2: checks and scatter
-    int64_t m = module_of(P.rec_mod_off, P.M, s_m0, rb < r1 ? rb : r0);
-    uint32_t maxid = 0;
-    int64_t maxid_m = m;
-    for (int k = 0; k < rpt; ++k) {
-      int64_t r = rb + k;
-      if (r >= r1) break;
-      m = module_of(P.rec_mod_off, P.M, m, r);
-      if (m != maxid_m) {
-        if (maxid) atomicMax(&P.mod_maxid[maxid_m], maxid);
-        maxid = 0;
-        maxid_m = m;
-      }
-      if (r == P.rec_mod_off[m]) {
-        // first record of module m (and of the empty modules just before it)
-        for (int64_t mm = m; mm >= 0 && P.rec_mod_off[mm] == r; --mm) P.mod_words[mm] = int64_t(S);
-      }
-      uint32_t op = P.op[r];
-      int64_t o0 = P.opnd_off[r];
-      int64_t n_ops = int64_t(P.opnd_off[r + 1]) - o0;
-      int64_t s0 = P.str_off[r];
-      int64_t L = int64_t(P.str_off[r + 1]) - s0;
-      uint32_t e = tbl[op < 256u ? op : 256u];
-      bool known = (e & 0x8000u) != 0;
-      bool name = (e >> 8) & 1u;
-      uint32_t idm = (e >> 4) & 0xFu;
-      int64_t sw = (name || L > 0) ? L / 4 + 1 : 0;
-      int64_t wc = 1 + n_ops + sw;
-      uint32_t code = 0;
-      if (!known) code = SPV_ENC_UNKNOWN_OPCODE;
-      else if (n_ops != int64_t(e & 0xFu)) code = SPV_ENC_OPERAND_COUNT;
-      else if (!name && L > 0) code = SPV_ENC_BAD_STRING;
-      else {
-        for (int64_t i = 0; i < L && code == 0; ++i)
-          if (P.chars[s0 + i] == 0) code = SPV_ENC_BAD_STRING;
-        if (code == 0 && wc > 65535) code = SPV_ENC_TOO_LONG;
-      }
-      int64_t base = 5 * (m + 1) + int64_t(S);
-      bool fits = base + wc <= P.words_cap;
-      if (fits) P.words_out[base] = uint32_t((wc & 0xFFFF) << 16) | (op & 0xFFFFu);
-      for (int64_t i = 0; i < n_ops; ++i) {
-        uint32_t v = P.opnd[o0 + i];
-        if (code == 0 && i < 4 && ((idm >> i) & 1u)) {
-          if (v == 0xFFFFFFFFu) code = SPV_ENC_BAD_ID;
-          else if (v + 1u > maxid) maxid = v + 1u;
-        }
-        if (fits) P.words_out[base + 1 + i] = v;
-      }
-      for (int64_t s = 0; s < sw; ++s) {
-        uint32_t word = 0;
-        for (int bb = 0; bb < 4; ++bb) {
-          int64_t ci = 4 * s + bb;
-          uint32_t byte = ci < L ? P.chars[s0 + ci] : 0u;
-          word |= byte << (8 * bb);
-        }
-        if (fits) P.words_out[base + 1 + n_ops + s] = word;
-      }
-      if (code) atomicMin(&P.mod_bad[m], ((unsigned long long)(r - P.rec_mod_off[m]) << 8) | code);
-      S += uint64_t(wc);
-    }
-    if (maxid) atomicMax(&P.mod_maxid[maxid_m], maxid);
-    __syncthreads();
   }
 }
 
@@ -257,7 +406,7 @@ __global__ __launch_bounds__(256) void k_enc_fin(EParams P) {
   const int64_t gtid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const int64_t nth = int64_t(gridDim.x) * blockDim.x;
   unsigned long long total = 0;
-  if (P.n_blocks > 0) total = P.blk[P.n_blocks - 1] & kESum;
+  if (P.n_blocks > 0) total = P.blkx[P.n_blocks];
   for (int64_t m = gtid; m < P.M; m += nth) {
     int64_t s_m = P.mod_words[m];
     if (s_m < 0) s_m = int64_t(total);  // trailing modules without records
@@ -355,7 +504,11 @@ void launch_encode(const EParams& p, int grid, hipStream_t s) {
   int64_t gi = (p.M > p.n_blocks ? p.M : p.n_blocks) / 256 + 1;
   int ginit = int(gi > 4096 ? 4096 : gi);
   hipLaunchKernelGGL(k_enc_init, dim3(ginit), dim3(256), 0, s, p);
-  if (p.n_blocks > 0) hipLaunchKernelGGL(k_enc_main, dim3(grid), dim3(kEncThreads), 0, s, p);
+  if (p.n_blocks > 0) {
+    hipLaunchKernelGGL(k_enc_count, dim3(grid), dim3(kEncThreads), 0, s, p);
+    hipLaunchKernelGGL(k_enc_scan, dim3(int(p.n_blocks / kEncThreads + 1)), dim3(kEncThreads), 0, s, p);
+    hipLaunchKernelGGL(k_enc_scatter, dim3(grid), dim3(kEncThreads), 0, s, p);
+  }
   int64_t gf = p.M / 256 + 1;
   hipLaunchKernelGGL(k_enc_fin, dim3(int(gf > 4096 ? 4096 : gf)), dim3(256), 0, s, p);
   hipLaunchKernelGGL(k_enc_compact, dim3(1), dim3(256), 0, s, p);

@@ -206,7 +206,10 @@ struct EParams {
   int64_t* enc_bad;
   // workspace
   uint32_t* ctrl;
-  unsigned long long* blk;    // per-block look-back state
+  unsigned long long* blk;    // per block of records: word total
+  unsigned long long* blkx;   // per block of records: words of all records before it (+ grand total)
+  unsigned long long* sstate; // look-back states of the scan of the totals
+  int64_t* bmod;              // per block of records: module of its first record
   unsigned long long* mod_bad;   // per module: (record << 8) | code, atomicMin
   uint32_t* mod_maxid;        // per module: max ID operand + 1 (atomicMax)
   int64_t* mod_words;         // per module: optimistic start offset of its first record
@@ -216,7 +219,7 @@ struct EParams {
 };
 
 struct ELayout {
-  size_t ctrl, blk, mod_bad, mod_maxid, mod_words, total;
+  size_t ctrl, blk, blkx, sstate, bmod, mod_bad, mod_maxid, mod_words, total;
 };
 
 inline ELayout make_elayout(int64_t n_modules, int64_t n_records, int block_records) {
@@ -226,6 +229,12 @@ inline ELayout make_elayout(int64_t n_modules, int64_t n_records, int block_reco
   L.ctrl = off;
   off = align256(off + 256);
   L.blk = off;
+  off = align256(off + 8 * size_t(nb + 1));
+  L.blkx = off;
+  off = align256(off + 8 * size_t(nb + 2));
+  L.sstate = off;
+  off = align256(off + 128 * size_t(nb / 256 + 2));
+  L.bmod = off;
   off = align256(off + 8 * size_t(nb + 1));
   L.mod_bad = off;
   off = align256(off + 8 * size_t(n_modules + 1));
