@@ -112,7 +112,7 @@ const char *spv_last_hip_error(spv_ctx *ctx);
  * persistent grid of the single-pass decode/validate walk (a value above the
  * kernel's resident blocks per CU also turns off its cooperative, static tile
  * order); encode_block sets the records per encode block (a multiple of 256,
- * at most 4096; SPV_ERR_INVALID_ARG otherwise). */
+ * at most 4096, default 4096; SPV_ERR_INVALID_ARG otherwise). */
 int spv_set_tuning(spv_ctx *ctx, int blocks_per_cu, int encode_block);
 /* Current launch tuning of the context. */
 int spv_get_tuning(spv_ctx *ctx, int *blocks_per_cu, int *encode_block);

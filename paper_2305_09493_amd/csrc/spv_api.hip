@@ -17,6 +17,8 @@ struct spv_ctx {
   int chain_occ;       // resident blocks per CU of the chain pass
   int walk_occ;        // resident blocks per CU of the resolved walk
   int encode_block;    // records per encode block
+  int enc_count_occ;   // resident blocks per CU of the encoder's count pass
+  int enc_scatter_occ; // resident blocks per CU of the encoder's scatter pass
   hipError_t last;
   char msg[256];
   bool timing;
@@ -28,6 +30,7 @@ namespace spv {
 int main_occupancy();
 int chain_occupancy();
 int walk_occupancy();
+int encode_occupancy(int pass);
 }
 
 namespace {
@@ -198,8 +201,12 @@ int spv_create(spv_ctx** out, int hip_device) {
     int wocc = spv::walk_occupancy();
     c->walk_occ = wocc > 0 ? wocc : 2;
     c->blocks_per_cu = occ > 0 ? (occ < 8 ? occ : 8) : 2;
+    int eo = spv::encode_occupancy(0);
+    c->enc_count_occ = eo > 0 ? eo : 2;
+    eo = spv::encode_occupancy(1);
+    c->enc_scatter_occ = eo > 0 ? eo : 2;
   }
-  c->encode_block = 1024;
+  c->encode_block = 4096;
   c->last = hipSuccess;
   c->msg[0] = '\0';
   c->timing = false;
@@ -339,9 +346,12 @@ int spv_encode(spv_ctx* ctx, const uint16_t* op, const int32_t* opnd_off, const 
   p.stage = nullptr;
   p.block_records = ctx->encode_block;
   p.n_blocks = (n_records + ctx->encode_block - 1) / ctx->encode_block;
-  int64_t grid = int64_t(ctx->n_cu) * 8;
-  if (grid > p.n_blocks) grid = p.n_blocks;
-  spv::launch_encode(p, int(grid > 0 ? grid : 1), static_cast<hipStream_t>(stream));
+  // persistent grids of exactly the resident blocks: every block takes the
+  // same share of record blocks, with no second partial round
+  int64_t gc = int64_t(ctx->n_cu) * ctx->enc_count_occ, gs = int64_t(ctx->n_cu) * ctx->enc_scatter_occ;
+  if (gc > p.n_blocks) gc = p.n_blocks;
+  if (gs > p.n_blocks) gs = p.n_blocks;
+  spv::launch_encode(p, int(gc > 0 ? gc : 1), int(gs > 0 ? gs : 1), static_cast<hipStream_t>(stream));
   return check_launch(ctx);
 }
 

@@ -219,10 +219,15 @@ __global__ __launch_bounds__(kEncThreads) void k_enc_scan(EParams P) {
   if (i <= P.n_blocks) P.blkx[i] = ex;  // (blkx[n_blocks]: the grand total)
 }
 
-// Pass 3: checks and scatter.  kEncChunk slices of 256 records per step:
-// the fields and operands of all of a thread's records of the step are loaded
-// before any is used, and one block scan gives all their positions.  One
-// slice per step measured fastest (more slices cost occupancy).
+// Pass 3: checks and scatter.  A block takes its records in steps of
+// kEncChunk slices of 256 consecutive records: the record fields and the
+// operands of all of a thread's records of the step are loaded before any is
+// used, one block scan gives their positions, and every thread then writes
+// its records' words.  One slice per step measured fastest: more slices cost
+// more registers than the extra loads in flight gain.  Staging a step's
+// operand, character and output runs in LDS (coalesced copies in and out)
+// measured slower still: the scatter is bound by dependent memory round
+// trips, and staging adds barriers without removing any.
 constexpr int kEncChunk = 1;
 
 __global__ __launch_bounds__(kEncThreads) void k_enc_scatter(EParams P) {
@@ -242,14 +247,14 @@ __global__ __launch_bounds__(kEncThreads) void k_enc_scatter(EParams P) {
     unsigned long long base_s = P.blkx[b];  // words of all records before this block
     const int64_t m0 = P.bmod[b];
     // starts of the modules from m0 on, so that finding a record's module
-    // costs LDS reads; beyond the staged range the offsets are read from HBM
+    // costs LDS reads when all the block's module starts are among them, else
+    // the searches read HBM (a block-uniform choice: no access mixes the two)
     __syncthreads();  // the previous block's reads of s_off are done
     s_off[tid] = (m0 + tid <= P.M) ? P.rec_mod_off[m0 + tid] : INT64_MAX;
     if (tid == 0) s_off[kEncThreads] = (m0 + kEncThreads <= P.M) ? P.rec_mod_off[m0 + kEncThreads] : INT64_MAX;
     __syncthreads();
-    auto off_at = [&](int64_t i) -> int64_t {  // rec_mod_off[m0 + i]
-      return (i >= 0 && i <= kEncThreads) ? s_off[i] : P.rec_mod_off[m0 + i];
-    };
+    const int64_t rblast = (r0 + P.block_records < P.N ? r0 + P.block_records : P.N) - 1;
+    const bool lds_mods = s_off[kEncThreads] > rblast;
     int64_t ml = 0;  // this thread's current module, relative to m0
     for (int k0 = 0; k0 < rpt; k0 += kEncChunk) {
       int64_t r[kEncChunk], o0[kEncChunk], n_ops[kEncChunk], s0[kEncChunk], L[kEncChunk];
@@ -305,11 +310,17 @@ __global__ __launch_bounds__(kEncThreads) void k_enc_scatter(EParams P) {
       for (int j = 0; j < kEncChunk; ++j) {
         if (!real[j]) continue;
         // module of r (forward from the block's first module)
-        while (m0 + ml + 1 < P.M && off_at(ml + 1) <= r[j]) ++ml;
+        bool first;
+        if (lds_mods) {
+          while (m0 + ml + 1 < P.M && s_off[ml + 1] <= r[j]) ++ml;
+          first = r[j] == s_off[ml];
+        } else {
+          while (m0 + ml + 1 < P.M && P.rec_mod_off[m0 + ml + 1] <= r[j]) ++ml;
+          first = r[j] == P.rec_mod_off[m0 + ml];
+        }
         const int64_t mr = m0 + ml;
-        if (r[j] == off_at(ml)) {
-          // first record of module mr (and of the empty modules just before it)
-          for (int64_t mm = ml; m0 + mm >= 0 && off_at(mm) == r[j]; --mm) P.mod_words[m0 + mm] = int64_t(S[j]);
+        if (first) {
+          for (int64_t mm = mr; mm >= 0 && P.rec_mod_off[mm] == r[j]; --mm) P.mod_words[mm] = int64_t(S[j]);
         }
         if (mr != max_m) {
           if (maxid) atomicMax(&P.mod_maxid[max_m], maxid);
@@ -356,8 +367,8 @@ __global__ __launch_bounds__(kEncThreads) void k_enc_scatter(EParams P) {
         // safe to read), eight output words at a time, all loads issued before
         // use, and realigned with a byte funnel shift.
         if (sw > 0) {
-          const uint32_t* cw = reinterpret_cast<const uint32_t*>(reinterpret_cast<uintptr_t>(P.chars + s0[j]) & ~uintptr_t(3));
           const uint32_t sh = uint32_t(reinterpret_cast<uintptr_t>(P.chars + s0[j]) & 3u);
+          const uint32_t* cw = reinterpret_cast<const uint32_t*>(P.chars + s0[j] - sh);
           for (int64_t s8 = 0; s8 < sw; s8 += 8) {
             const int64_t need = (L[j] - 4 * s8 + int64_t(sh) + 3) / 4;  // aligned words holding characters
             uint32_t a[9];
@@ -384,7 +395,7 @@ __global__ __launch_bounds__(kEncThreads) void k_enc_scatter(EParams P) {
         if (code) atomicMin(&P.mod_bad[mr], ((unsigned long long)(r[j] - P.rec_mod_off[mr]) << 8) | code);
       }
       // bound: max ID + 1 per module (one atomic per wave when the wave's
-      // records of this chunk are in one module)
+      // records of this step are in one module)
       const int64_t mlead = __shfl(max_m, 0);
       if (__ballot(max_m != mlead) == 0 && mlead >= 0) {
         uint32_t mx = maxid;
@@ -500,14 +511,21 @@ __global__ __launch_bounds__(256) void k_enc_compact(EParams P) {
   if (tid == 0) P.word_mod_off[P.M] = s_run;
 }
 
-void launch_encode(const EParams& p, int grid, hipStream_t s) {
+int encode_occupancy(int pass) {
+  int n = 0;
+  const void* k = pass == 0 ? reinterpret_cast<const void*>(k_enc_count) : reinterpret_cast<const void*>(k_enc_scatter);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, kEncThreads, 0) != hipSuccess) return 0;
+  return n;
+}
+
+void launch_encode(const EParams& p, int grid_count, int grid_scatter, hipStream_t s) {
   int64_t gi = (p.M > p.n_blocks ? p.M : p.n_blocks) / 256 + 1;
   int ginit = int(gi > 4096 ? 4096 : gi);
   hipLaunchKernelGGL(k_enc_init, dim3(ginit), dim3(256), 0, s, p);
   if (p.n_blocks > 0) {
-    hipLaunchKernelGGL(k_enc_count, dim3(grid), dim3(kEncThreads), 0, s, p);
+    hipLaunchKernelGGL(k_enc_count, dim3(grid_count), dim3(kEncThreads), 0, s, p);
     hipLaunchKernelGGL(k_enc_scan, dim3(int(p.n_blocks / kEncThreads + 1)), dim3(kEncThreads), 0, s, p);
-    hipLaunchKernelGGL(k_enc_scatter, dim3(grid), dim3(kEncThreads), 0, s, p);
+    hipLaunchKernelGGL(k_enc_scatter, dim3(grid_scatter), dim3(kEncThreads), 0, s, p);
   }
   int64_t gf = p.M / 256 + 1;
   hipLaunchKernelGGL(k_enc_fin, dim3(int(gf > 4096 ? 4096 : gf)), dim3(256), 0, s, p);

@@ -246,6 +246,6 @@ inline ELayout make_elayout(int64_t n_modules, int64_t n_records, int block_reco
   return L;
 }
 
-void launch_encode(const EParams& p, int grid, hipStream_t s);
+void launch_encode(const EParams& p, int grid_count, int grid_scatter, hipStream_t s);
 
 }  // namespace spv

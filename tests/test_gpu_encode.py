@@ -51,10 +51,10 @@ def test_encode_block_sizes():
     import paper_2305_09493_amd as spv
     mods = [spvgen.gen_module([21, i], 3000) for i in range(8)]
     r = spvgen.pack_records(mods)
-    for blk in (256, 512, 2048):
+    for blk in (256, 1024, 2048):
         spv.context().set_tuning(encode_block=blk)
         _check(r, f"block {blk}")
-    spv.context().set_tuning(encode_block=1024)
+    spv.context().set_tuning(encode_block=4096)
 
 
 def test_encode_failures_compacted():
@@ -89,3 +89,54 @@ def test_encode_empty_modules_and_versions():
     rmo = r["rec_mod_off"]
     r["rec_mod_off"] = np.concatenate([[0, 0], rmo[1:2], rmo[1:2], rmo[2:], rmo[-1:]]).astype(np.int64)
     _check(r, "empty modules", version_word=0x00010200, generator_word=32)
+
+
+def _records(mods):
+    """CSR records from modules given as lists of (opcode, operands, name bytes)."""
+    op, oo, od, so, ch, rmo = [], [0], [], [0], [], [0]
+    for recs in mods:
+        for opcode, operands, name in recs:
+            op.append(opcode)
+            od.extend(operands)
+            oo.append(len(od))
+            ch.append(name)
+            so.append(so[-1] + len(name))
+        rmo.append(len(op))
+    chars = np.frombuffer(b"".join(ch), dtype=np.uint8).copy()
+    return dict(op=np.array(op, np.uint16), opnd_off=np.array(oo, np.int32), opnd=np.array(od, np.uint32),
+                str_off=np.array(so, np.int32), chars=chars, rec_mod_off=np.array(rmo, np.int64))
+
+
+def _plain_module(rng, n):
+    recs = [(17, [6], b""), (14, [2, 2], b""), (21, [1, 32, 0], b"")]
+    nid = 2
+    for _ in range(n - 3):
+        k = int(rng.integers(0, 3))
+        if k == 0:
+            recs.append((5, [int(rng.integers(1, nid))], rng.integers(97, 123, size=int(rng.integers(0, 30))).astype(np.uint8).tobytes()))
+        elif k == 1:
+            recs.append((43, [1, nid, int(rng.integers(0, 1 << 32))], b""))
+            nid += 1
+        else:
+            recs.append((62, [int(rng.integers(1, nid)), int(rng.integers(1, nid))], b""))
+    return recs
+
+
+def test_encode_runs_beyond_lds_staging():
+    """Slices whose operand, character or output runs exceed what one step
+    stages in LDS: long names, operand-count errors with many operands, a
+    record over 65535 words, and blocks that hold hundreds of module starts."""
+    rng = np.random.default_rng(24)
+    mods = [_plain_module(rng, 700) for _ in range(3)]
+    mods[0][100] = (5, [1], b"n" * 3000)             # 751 string words in one record
+    mods[0][400] = (5, [1], b"a" * 1500)
+    mods[0][401] = (5, [1], b"b" * 1501)
+    mods[1][200] = (62, list(range(1, 2001)), b"")   # operand count error, 2000 operands
+    mods[2][300] = (5, [1], b"x" * 270000)           # 1 + 1 + 67501 words: too long
+    tiny = [_plain_module(rng, 3) for _ in range(700)]
+    tiny[10] = []                                     # empty modules among tiny ones
+    tiny[11] = []
+    r = _records(mods + tiny + [_plain_module(rng, 900)])
+    _check(r, "beyond staging")
+    r = _records([mods[0], mods[2]] + tiny)
+    _check(r, "beyond staging 2", version_word=0x00010500)
