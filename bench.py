@@ -120,15 +120,16 @@ def serve_leg(args):
     log(f"serving leg: pool of {args.serve_pool} modules (lognormal median 5000 instructions, max 1M)")
     pool = [m.words for m in spvgen.serving_pool(n_pool=args.serve_pool)]
     out = []
+    warm = args.serve_warmup
     for rate in [float(x) for x in args.serve_rates.split(",")]:
-        arr = spvgen.poisson_arrivals(rate, args.serve_seconds)
+        arr = spvgen.poisson_arrivals(rate, warm + args.serve_seconds)
         pick = np.random.default_rng([5, int(rate)]).integers(0, len(pool), size=arr.size)
-        row = {"rate_per_s": rate, "seconds": args.serve_seconds}
+        row = {"rate_per_s": rate, "seconds": args.serve_seconds, "warmup_s": warm}
         for mode, kw in (("batched", dict(max_batch_modules=4096, n_slots=4)),
                          ("batched_graphs", dict(max_batch_modules=4096, n_slots=4, use_graphs=True)),
                          ("one_per_launch", dict(max_batch_modules=1, n_slots=4))):
             log(f"  rate {rate:.0f}/s {mode}")
-            _, summ = run_trace(pool, arr, pick, **kw)
+            _, summ = run_trace(pool, arr, pick, warmup_s=warm, **kw)
             row[mode] = {k: summ[k] for k in ("requests", "words_per_s", "p50_ms", "p99_ms", "mean_batch",
                                              "server_batches")}
         out.append(row)
@@ -150,13 +151,16 @@ def main():
     ap.add_argument("--serve", action="store_true", help="add the serving leg (Poisson stream, batched vs "
                                                          "one module per launch)")
     ap.add_argument("--serve-rates", default="20000", help="comma-separated arrival rates for --serve")
-    ap.add_argument("--serve-seconds", type=float, default=3.0)
+    ap.add_argument("--serve-seconds", type=float, default=3.0, help="measured seconds per rate")
+    ap.add_argument("--serve-warmup", type=float, default=1.0,
+                    help="seconds of arrivals served before the measured ones and left out of p50/p99")
     ap.add_argument("--serve-pool", type=int, default=2048)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (see the design notes on "
-              "how the path would shard)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path (batches would shard by a "
+              "word-balanced cut of the module CSR, one large module by word ranges with one exchange of tile "
+              "states)", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -8,29 +8,33 @@
 // storing a module (section "Validation Rules") together with the SSA rule
 // that every ID is defined once (section "Enabling Function Composition").
 //
-// How (MI355X design, see the design notes of the repository):
+// How (MI355X design):
 //   * The batch's words are cut into tiles of 4096 words, 16 per lane, 256
-//     lanes per block; tiles ignore module boundaries.  A persistent grid
-//     claims tiles in order from an atomic counter.
+//     lanes per block; tiles ignore module boundaries.
 //   * Instruction-boundary recovery is pointer jumping over
-//     next(i) = i + (w[i] >> 16).  Each lane runs it backwards over its 16
-//     words once, keeping the exits of the 15 following positions as a
-//     packed 4-bit table in a 64-bit register, which yields the lane's
-//     transfer function "entry offset -> exit offset".  Chains that start on
-//     operand words die at once (implausible starts), so almost every lane's
-//     function is constant over its surviving entries; such lanes, waves and
-//     tiles publish their exit without knowing their entry, and the only
-//     serial resolution left is over runs of ambiguous lanes.
-//   * Tiles chain through a decoupled look-back (aggregate / full states in
-//     the workspace) for the exact entry and for the per-module instruction
-//     count that ranks the index entries.
-//   * Tiles with an instruction longer than 14 words on their chain, or with
-//     more than 256 module starts, take a serial per-tile path.
+//     next(i) = i + (w[i] >> 16).  Each lane derives its transfer function
+//     "entry offset -> exit offset" over its 16 words: by following the
+//     chain from its first plausible start when every plausible start lies on
+//     that chain (chains that start on operand words die at once, so this is
+//     the common case and the exit does not depend on the entry), else by a
+//     backward recurrence that packs the exits of the 15 following positions
+//     as 4-bit nibbles in a 64-bit register.
+//   * Three passes when every tile settles this way (the common case): the
+//     chain pass computes every tile's exit, its lanes' starts and its
+//     per-module start counts, each tile on its own; the resolve pass scans
+//     the tile summaries (a segmented scan chained by a decoupled look-back)
+//     into every tile's exact entry and instruction-count prefix; the walk
+//     then checks, indexes and marks result IDs with no waiting between
+//     tiles.  Otherwise (a tile with an instruction of 15+ words on a
+//     candidate chain, crowded module starts, a lane that stays ambiguous)
+//     the whole batch takes the single-pass walk, in which tiles chain
+//     through a decoupled look-back on aggregate / full states; tiles that
+//     even this cannot settle are walked serially by one thread.
 //   * Result-ID define-once checks use 64-bit bitmaps (or a hash table when
-//     the bound is much larger than the module) with atomics; the
-//     undefined-ID check is skipped for modules whose result IDs cover
-//     [1, bound) (no use can then be undefined) and otherwise runs as a
-//     second pass against the completed bitmap.
+//     the bound is much larger than the module) with atomics, accumulated in
+//     LDS windows first; the undefined-ID check is skipped for modules whose
+//     result IDs cover [1, bound) (no use can then be undefined) and
+//     otherwise runs as a second pass against the completed bitmap.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 

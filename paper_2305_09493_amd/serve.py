@@ -129,9 +129,12 @@ class Server:
         self.close()
 
 
-def run_trace(modules: List[np.ndarray], arrivals_s: np.ndarray, pick: np.ndarray, **server_kw):
+def run_trace(modules: List[np.ndarray], arrivals_s: np.ndarray, pick: np.ndarray, warmup_s: float = 0.0,
+              **server_kw):
     """Replay a Poisson trace: request i is modules[pick[i]] arriving at
-    arrivals_s[i].  Returns (completions, summary dict)."""
+    arrivals_s[i].  Requests arriving before warmup_s are served but left out
+    of the summary (first graph captures, first touches of the staging
+    buffers).  Returns (completions, summary dict)."""
     with Server(**server_kw) as srv:
         reqs = [modules[j] for j in pick]
         srv.submit(reqs, ids=np.arange(len(reqs)), t_arrival_s=arrivals_s)
@@ -140,13 +143,17 @@ def run_trace(modules: List[np.ndarray], arrivals_s: np.ndarray, pick: np.ndarra
         comp = srv.drain(timeout_s=max(120.0, 4 * float(arrivals_s[-1]) if len(arrivals_s) else 120.0))
         wall = time.time() - t0
         st = srv.stats()
+    all_comp = comp
+    if warmup_s > 0 and comp.size:
+        keep = arrivals_s[comp["id"]] >= warmup_s
+        comp = comp[keep]
     lat_ms = (comp["t_done_ns"] - comp["t_arrival_ns"]) / 1e6
-    words = int(sum(modules[j].size for j in pick))
+    words = int(sum(modules[pick[i]].size for i in comp["id"])) if comp.size else 0
     span_s = (comp["t_done_ns"].max() - comp["t_arrival_ns"].min()) / 1e9 if comp.size else 0.0
     summary = dict(requests=int(comp.size), words=words, span_s=float(span_s), wall_s=wall,
                    words_per_s=words / span_s if span_s > 0 else 0.0,
                    p50_ms=float(np.percentile(lat_ms, 50)) if comp.size else None,
                    p99_ms=float(np.percentile(lat_ms, 99)) if comp.size else None,
                    mean_batch=float(comp["batch_modules"].mean()) if comp.size else None,
-                   **{"server_" + k: v for k, v in st.items()})
-    return comp, summary
+                   warmup_s=warmup_s, **{"server_" + k: v for k, v in st.items()})
+    return all_comp, summary
