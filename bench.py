@@ -47,8 +47,13 @@ def log(msg):
 
 
 def kernel_source_sha():
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Fingerprint of the kernel code: sha256 of the source with // comments,
+    trailing blanks and empty lines removed (comment edits keep it)."""
+    import re
+    with open(KERNEL_SRC) as f:
+        lines = [re.sub(r"\s*//.*$", "", ln).rstrip() for ln in f]
+    code = "\n".join(ln for ln in lines if ln)
+    return hashlib.sha256(code.encode()).hexdigest()[:16]
 
 
 def traffic_from_counters(n_words, n_inst):
