@@ -2,8 +2,8 @@
 so they can be captured in a HIP graph: capture spv_validate once, replay it
 several times on new inputs of the same shape (with eager work and
 synchronisations between replays) and check every replay against the eager
-result and the oracle.  Also: parity does not depend on the persistent grid
-size."""
+result and the oracle; the same for spv_encode.  Also: parity does not
+depend on the persistent grid size."""
 import numpy as np
 import pytest
 
@@ -69,6 +69,57 @@ def test_graph_capture_replays_match_eager():
         exp = np.stack([o[k] for k in ("code", "sem_mask", "err_word", "n_inst")], axis=1)
         assert np.array_equal(got, r2.cpu().numpy().view(np.uint32)), seed
         assert np.array_equal(got, exp), seed
+        _ = torch.ones(1 << 20, device="cuda").sum().item()  # unrelated eager work between replays
+
+
+def _records_variant(r0, seed):
+    """Records of the same shape as r0 (same counts and lengths) with new
+    name characters; odd seeds also put an ID operand of 0xFFFFFFFF into one
+    record (a failing module, so the replay also compacts)."""
+    r = {k: v.copy() for k, v in r0.items()}
+    if seed:
+        rng = np.random.default_rng([41, seed])
+        r["chars"] = rng.integers(97, 123, size=r["chars"].size).astype(np.uint8)
+        if seed % 2:
+            stores = np.nonzero(r["op"] == 62)[0]
+            j = int(stores[(37 * seed) % stores.size])
+            r["opnd"][r["opnd_off"][j]] = 0xFFFFFFFF
+    return r
+
+
+def test_encode_graph_capture_replays_match_eager():
+    import torch
+
+    import paper_2305_09493_amd as spv
+    r0 = spvgen.pack_records([spvgen.gen_module([41, i], 2000) for i in range(6)])
+    d = {k: torch.from_numpy(r0[k].view(np.int16) if k == "op" else
+                             r0[k].view(np.int32) if k == "opnd" else r0[k]).cuda() for k in r0}
+    spv.encode(**d)  # warm-up outside capture (sizes the context's workspace)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            gout = spv.encode(**d, stream=s)
+    torch.cuda.synchronize()
+    for seed in range(1, 5):
+        r = _records_variant(r0, seed)
+        d["chars"].copy_(torch.from_numpy(r["chars"]))
+        d["opnd"].copy_(torch.from_numpy(r["opnd"].view(np.int32)))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        gw, gmo, gc, gb = [t.cpu().numpy() for t in gout]
+        ew, emo, ec, eb = [t.cpu().numpy() for t in spv.encode(**d)]
+        torch.cuda.synchronize()
+        ow, omo, oc, ob = oracle.encode(**r)
+        n = int(gmo[-1])
+        assert np.array_equal(gmo, emo) and np.array_equal(gmo, omo), seed
+        assert np.array_equal(gc, ec) and np.array_equal(gc.astype(np.uint32), oc), seed
+        assert np.array_equal(gb, eb) and np.array_equal(gb, ob), seed
+        assert np.array_equal(gw.view(np.uint32)[:n], ow) and np.array_equal(ew.view(np.uint32)[:n], ow), seed
+        if seed % 2:
+            assert (oc != 0).sum() == 1, seed
         _ = torch.ones(1 << 20, device="cuda").sum().item()  # unrelated eager work between replays
 
 
