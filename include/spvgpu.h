@@ -39,7 +39,7 @@ extern "C" {
 /* ---- call status ------------------------------------------------------- */
 #define SPV_SUCCESS 0
 #define SPV_ERR_INVALID_ARG (-1) /* null pointer, negative size, misaligned words, bad flags */
-#define SPV_ERR_CAPACITY (-2)    /* idx_cap < n_words, or words_cap < spv_encode_bound */
+#define SPV_ERR_CAPACITY (-2)    /* idx_cap < n_words, or words_cap < 5*n_modules + n_records */
 #define SPV_ERR_WORKSPACE (-3)   /* ws too small (see spv_workspace_size) or null */
 #define SPV_ERR_HIP (-4)         /* a HIP runtime call failed; see spv_last_hip_error */
 #define SPV_ERR_LIMIT (-5)       /* a module has >= 2^32 words, or too many modules */
@@ -80,6 +80,13 @@ extern "C" {
 #define SPV_ENC_BAD_STRING 3     /* string on a non-OpName record, or NUL inside an OpName string */
 #define SPV_ENC_TOO_LONG 4       /* word count would exceed 65535 */
 #define SPV_ENC_BAD_ID 5         /* an ID operand equals 0xFFFFFFFF (bound not representable) */
+#define SPV_ENC_CAPACITY 6       /* the module would end past words_cap (its words are not kept) */
+
+/* Result code (decode / validate code or encode status) of every module of a
+ * call in which a kernel's wait on another block exceeded its spin limit
+ * (a scheduling failure, not a property of the input); the call's outputs
+ * are then not valid and the call may be repeated. */
+#define SPV_E_SPIN_LIMIT 0xDEAD
 
 /* Grammar table (the twelve opcodes of the synthetic workloads): opcode,
  * word count, operand roles (U = ID use, D = result ID, L = literal,
@@ -164,7 +171,10 @@ int spv_encode_workspace_size(spv_ctx *ctx, int64_t n_modules, int64_t n_records
  * A module with a failing record writes no words; enc_code[m] /
  * enc_bad_record[m] (module-relative index of its first failing record, -1
  * if none) say why.  word_mod_off (n_modules+1) receives the dense output
- * CSR.  words_cap must be >= spv_encode_bound(...).
+ * CSR.  words_cap >= spv_encode_bound(...) always suffices; a smaller one
+ * (at least 5*n_modules + n_records, else SPV_ERR_CAPACITY) is accepted, and
+ * every module that would end past it gets SPV_ENC_CAPACITY (with a record
+ * index of -1) and no words, the modules before it keeping theirs.
  * Device pointers: op uint16[n_records], opnd_off int32[n_records+1],
  * opnd uint32[opnd_off[n]], str_off int32[n_records+1], chars uint8,
  * rec_mod_off int64[n_modules+1], words_out uint32[words_cap],
@@ -177,8 +187,9 @@ int spv_encode(spv_ctx *ctx, const uint16_t *op, const int32_t *opnd_off, const 
                void *stream);
 
 /* Measurement hook.  When enabled, every spv_decode / spv_validate call on
- * this context records a pair of HIP events around its instruction-walk
- * kernel (the dominant kernel) on the call's stream; spv_read_timing waits
+ * this context records a pair of HIP events on the call's stream around its
+ * boundary-recovery and walk kernels (chain pass, resolve pass, resolved
+ * walk, single-pass walk: the bulk of the call); spv_read_timing waits
  * for those events, returns their summed duration in milliseconds and the
  * number of launches since the last read, and clears them.  Not for use
  * inside graph capture. */

@@ -26,6 +26,8 @@ ERRORS = {-1: "invalid argument", -2: "capacity", -3: "workspace", -4: "HIP erro
 OK, E_TRUNCATED_HEADER, E_BAD_MAGIC, E_BAD_VERSION, E_BAD_SCHEMA = 0, 1, 2, 3, 4
 E_BAD_WORD_COUNT, E_UNKNOWN_OPCODE, E_BAD_STRING = 5, 6, 7
 E_ID_OUT_OF_BOUND, E_DUPLICATE_ID, E_UNDEFINED_ID = 8, 9, 10
+E_SPIN_LIMIT = 0xDEAD  # every result of a call whose inter-block wait gave up (repeat the call)
+ENC_OK, ENC_UNKNOWN_OPCODE, ENC_OPERAND_COUNT, ENC_BAD_STRING, ENC_TOO_LONG, ENC_BAD_ID, ENC_CAPACITY = range(7)
 
 _lib = None
 _lock = threading.Lock()

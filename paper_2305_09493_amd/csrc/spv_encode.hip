@@ -437,7 +437,7 @@ __global__ __launch_bounds__(256) void k_enc_fin(EParams P) {
       code = uint32_t(bad & 0xFFu);
       badrec = int64_t(bad >> 8);
     } else if (end > P.words_cap) {
-      code = 6;  // output capacity: the module does not fit in words_cap
+      code = SPV_ENC_CAPACITY;  // the module does not fit in words_cap
     }
     if (P.ctrl[2]) code = kSpinFailCode;
     P.enc_code[m] = code;

@@ -142,7 +142,7 @@ constexpr uint32_t kSumFallback = 1u << 31, kSumModStart = 1u << 30, kSumReset =
 // polls (seconds of waiting) and flags kCtlSpinErr instead of hanging; the
 // finalize kernel then marks every result with kSpinFailCode.
 constexpr uint32_t kSpinLimit = 1u << 22;
-constexpr uint32_t kSpinFailCode = 0xDEADu;
+constexpr uint32_t kSpinFailCode = SPV_E_SPIN_LIMIT;
 
 struct VParams {
   const uint32_t* words;

@@ -58,3 +58,16 @@ def test_gpu_tests_are_marked():
     for f in os.listdir(tdir):
         if f.startswith("test_gpu") and f.endswith(".py"):
             assert "pytestmark = pytest.mark.gpu" in open(os.path.join(tdir, f)).read(), f
+
+
+def test_binding_codes_match_header():
+    """The binding's result and encode-status constants equal the header's."""
+    import re
+
+    import paper_2305_09493_amd as spv
+    hdr = open(os.path.join(ROOT, "include", "spvgpu.h")).read()
+    defs = {m.group(1): int(m.group(2), 0) for m in re.finditer(r"#define (SPV_E_\w+|SPV_ENC_\w+|SPV_OK)\s+(\w+)", hdr)}
+    for name, value in defs.items():
+        py = name[len("SPV_"):]
+        assert getattr(spv, py) == value, name
+    assert {"SPV_E_SPIN_LIMIT", "SPV_ENC_CAPACITY", "SPV_E_UNDEFINED_ID"} <= set(defs)

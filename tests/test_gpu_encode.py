@@ -140,3 +140,23 @@ def test_encode_runs_beyond_lds_staging():
     _check(r, "beyond staging")
     r = _records([mods[0], mods[2]] + tiny)
     _check(r, "beyond staging 2", version_word=0x00010500)
+
+
+def test_encode_capacity_short_output():
+    """words_cap below the batch's total: the modules that fit are written as
+    the oracle writes them; every module that ends past words_cap reports
+    code 6 and writes nothing (the rest are compacted over it)."""
+    import torch
+    import paper_2305_09493_amd as spv
+    mods = [spvgen.gen_module([25, i], n) for i, n in enumerate([900, 1500, 700, 1200])]
+    r = spvgen.pack_records(mods)
+    ow, omo, oc, ob = oracle.encode(**r)
+    cap = int(omo[2]) + 3  # modules 0 and 1 fit; module 2 would end past the capacity
+    words, wmo, code, bad = spv.encode(**_dev(r), words_cap=cap)
+    torch.cuda.synchronize()
+    code = code.cpu().numpy()
+    wmo = wmo.cpu().numpy()
+    assert list(code) == [0, 0, 6, 6]
+    assert list(bad.cpu().numpy()) == [-1, -1, -1, -1]
+    assert np.array_equal(wmo[:3], omo[:3]) and wmo[3] == omo[2] and wmo[4] == omo[2]
+    assert np.array_equal(words.cpu().numpy().view(np.uint32)[:omo[2]], ow[:omo[2]])
