@@ -152,6 +152,32 @@ int spv_validate(spv_ctx *ctx, const uint32_t *words, const int64_t *mod_off, in
                  uint32_t *idx_off, uint16_t *idx_op, int64_t idx_cap, spv_result *results, uint32_t option_flags,
                  void *ws, size_t ws_bytes, void *stream);
 
+/* Bytes of workspace spv_decode_records needs. */
+int spv_records_workspace_size(spv_ctx *ctx, int64_t n_modules, int64_t n_words, size_t *bytes);
+
+/* Decode's records mode: the instructions a spv_decode / spv_validate call
+ * found, in the record layout spv_encode takes (the disassembler's
+ * instruction view, section "Dis/Assembler", in the form of the library's
+ * writer, section "SPIR-V Library").  Module m contributes the records of
+ * its valid instruction prefix, results[m].n_inst of them, or none when its
+ * header check failed (codes 1..4).  Record r: op[r] = its opcode; its
+ * non-string operand words opnd[opnd_off[r] .. opnd_off[r+1]) (OpName: its
+ * target ID); its string bytes chars[str_off[r] .. str_off[r+1]) (OpName:
+ * the name up to, not including, its NUL; none otherwise).  rec_mod_off
+ * receives the records' CSR by module; the record count is
+ * rec_mod_off[n_modules] (all -1 if a kernel's wait exceeded its spin limit).
+ * For a valid module, spv_encode of its records gives its words back.
+ *   words, mod_off : the batch the index was computed on (as for spv_decode)
+ *   idx_off, results : the index and results of that call (idx_op unused)
+ *   op uint16[n_words], opnd_off int32[n_words+1], opnd uint32[n_words],
+ *   str_off int32[n_words+1], chars uint8[4*n_words], rec_mod_off
+ *   int64[n_modules+1]: device buffers owned by the caller.
+ * n_words must be below 2^29 (SPV_ERR_LIMIT). */
+int spv_decode_records(spv_ctx *ctx, const uint32_t *words, const int64_t *mod_off, int64_t n_modules,
+                       int64_t n_words, const uint32_t *idx_off, const spv_result *results, uint16_t *op,
+                       int32_t *opnd_off, uint32_t *opnd, int32_t *str_off, uint8_t *chars, int64_t *rec_mod_off,
+                       void *ws, size_t ws_bytes, void *stream);
+
 /* Host-side upper bound on the words spv_encode may write:
  * 5*n_modules + n_records + n_opnd_words + n_string_records + n_chars/4. */
 int spv_encode_bound(int64_t n_modules, int64_t n_records, int64_t n_opnd_words, int64_t n_string_records,

@@ -59,6 +59,8 @@ def load_library():
         lib.spv_encode_bound.argtypes = [I64, I64, I64, I64, I64, ctypes.POINTER(I64)]
         lib.spv_encode_workspace_size.argtypes = [P, I64, I64, ctypes.POINTER(SZ)]
         lib.spv_encode.argtypes = [P, P, P, P, P, P, P, I64, I64, U32, U32, P, P, I64, P, P, P, SZ, P]
+        lib.spv_records_workspace_size.argtypes = [P, I64, I64, ctypes.POINTER(SZ)]
+        lib.spv_decode_records.argtypes = [P, P, P, I64, I64, P, P, P, P, P, P, P, P, P, SZ, P]
         lib.spv_set_timing.argtypes = [P, ctypes.c_int]
         lib.spv_get_tuning.argtypes = [P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
         lib.spv_read_timing.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)]
@@ -73,6 +75,7 @@ def load_library():
 
 EXPORTS = ("spv_create", "spv_destroy", "spv_last_hip_error", "spv_set_tuning", "spv_workspace_size",
            "spv_decode", "spv_validate", "spv_encode_bound", "spv_encode_workspace_size", "spv_encode",
+           "spv_records_workspace_size", "spv_decode_records",
            "spv_set_timing", "spv_read_timing", "spv_get_tuning", "spv_server_create", "spv_server_start", "spv_server_submit",
            "spv_server_poll", "spv_server_stats", "spv_server_destroy")
 
@@ -243,3 +246,32 @@ def encode(op, opnd_off, opnd, str_off, chars, rec_mod_off, version_word: int = 
                             words_cap, _ptr(code), _ptr(bad), _ptr(ws), ws.numel(), _stream(stream))
     ctx.check(rc, "spv_encode")
     return words, word_mod_off, code, bad
+
+
+def decode_records(words, mod_off, idx_off, results, ctx: Optional[Context] = None, stream=None):
+    """Decode's records mode: the records of every module's valid instruction
+    prefix, from the index (idx_off) and results of a decode / validate call
+    on the same batch, in the layout encode takes.  Returns a dict of CUDA
+    tensors sized for the batch's capacity (op, opnd_off, opnd, str_off,
+    chars, rec_mod_off); the record count is rec_mod_off[-1], read without a
+    host synchronisation here."""
+    torch = _torch()
+    ctx = ctx or context(words.device.index)
+    dev = words.device
+    W = int(words.numel())
+    M = int(mod_off.numel()) - 1
+    out = dict(op=torch.empty(max(W, 1), dtype=torch.int16, device=dev),
+               opnd_off=torch.empty(W + 1, dtype=torch.int32, device=dev),
+               opnd=torch.empty(max(W, 1), dtype=torch.int32, device=dev),
+               str_off=torch.empty(W + 1, dtype=torch.int32, device=dev),
+               chars=torch.empty(max(4 * W, 1), dtype=torch.uint8, device=dev),
+               rec_mod_off=torch.empty(M + 1, dtype=torch.int64, device=dev))
+    sz = ctypes.c_size_t()
+    ctx.check(ctx.lib.spv_records_workspace_size(ctx.h, M, W, ctypes.byref(sz)), "spv_records_workspace_size")
+    ws = ctx.workspace(sz.value)
+    rc = ctx.lib.spv_decode_records(ctx.h, _ptr(words), _ptr(mod_off), M, W, _ptr(idx_off), _ptr(results),
+                                    _ptr(out["op"]), _ptr(out["opnd_off"]), _ptr(out["opnd"]), _ptr(out["str_off"]),
+                                    _ptr(out["chars"]), _ptr(out["rec_mod_off"]), _ptr(ws), ws.numel(),
+                                    _stream(stream))
+    ctx.check(rc, "spv_decode_records")
+    return out

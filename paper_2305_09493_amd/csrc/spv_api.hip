@@ -296,6 +296,49 @@ int spv_encode_bound(int64_t n_modules, int64_t n_records, int64_t n_opnd_words,
   return SPV_SUCCESS;
 }
 
+int spv_records_workspace_size(spv_ctx* ctx, int64_t n_modules, int64_t n_words, size_t* bytes) {
+  if (!ctx || !bytes || n_modules < 0 || n_words < 0) return SPV_ERR_INVALID_ARG;
+  *bytes = spv::make_rlayout(n_modules, n_words).total;
+  return SPV_SUCCESS;
+}
+
+int spv_decode_records(spv_ctx* ctx, const uint32_t* words, const int64_t* mod_off, int64_t n_modules,
+                       int64_t n_words, const uint32_t* idx_off, const spv_result* results, uint16_t* op,
+                       int32_t* opnd_off, uint32_t* opnd, int32_t* str_off, uint8_t* chars, int64_t* rec_mod_off,
+                       void* ws, size_t ws_bytes, void* stream) {
+  if (!ctx || n_modules < 0 || n_words < 0) return SPV_ERR_INVALID_ARG;
+  if (n_words >= (int64_t(1) << 29)) return SPV_ERR_LIMIT;  // int32 string offsets: 4 bytes per word
+  if (n_modules >= (int64_t(1) << 31) - 1) return SPV_ERR_LIMIT;
+  if (n_modules == 0) return n_words == 0 ? SPV_SUCCESS : SPV_ERR_INVALID_ARG;
+  if (!mod_off || !results || !rec_mod_off || !opnd_off || !str_off) return SPV_ERR_INVALID_ARG;
+  if (n_words > 0 && (!words || !idx_off || !op || !opnd || !chars)) return SPV_ERR_INVALID_ARG;
+  spv::RLayout L = spv::make_rlayout(n_modules, n_words);
+  if (!ws || ws_bytes < L.total) return SPV_ERR_WORKSPACE;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail_hip(ctx, hipErrorInvalidDevice);
+  char* base = static_cast<char*>(ws);
+  spv::RParams p;
+  p.words = words;
+  p.mod_off = mod_off;
+  p.M = n_modules;
+  p.cap_records = n_words;
+  p.idx_off = idx_off;
+  p.results = results;
+  p.op = op;
+  p.opnd_off = opnd_off;
+  p.opnd = opnd;
+  p.str_off = str_off;
+  p.chars = chars;
+  p.rec_mod_off = rec_mod_off;
+  p.ctrl = reinterpret_cast<uint32_t*>(base + L.ctrl);
+  p.mscan = reinterpret_cast<unsigned long long*>(base + L.mscan);
+  p.mstate = reinterpret_cast<unsigned long long*>(base + L.mstate);
+  p.rscan = reinterpret_cast<unsigned long long*>(base + L.rscan);
+  p.rstate = reinterpret_cast<unsigned long long*>(base + L.rstate);
+  spv::launch_records(p, static_cast<hipStream_t>(stream));
+  return check_launch(ctx);
+}
+
 int spv_encode_workspace_size(spv_ctx* ctx, int64_t n_modules, int64_t n_records, size_t* bytes) {
   if (!ctx || !bytes || n_modules < 0 || n_records < 0) return SPV_ERR_INVALID_ARG;
   *bytes = spv::make_elayout(n_modules, n_records, ctx->encode_block).total;

@@ -248,4 +248,49 @@ inline ELayout make_elayout(int64_t n_modules, int64_t n_records, int block_reco
 
 void launch_encode(const EParams& p, int grid_count, int grid_scatter, hipStream_t s);
 
+// decode's records mode
+struct RParams {
+  const uint32_t* words;
+  const int64_t* mod_off;
+  int64_t M;
+  int64_t cap_records;  // n_words: no batch has more records
+  const uint32_t* idx_off;
+  const spv_result* results;
+  uint16_t* op;
+  int32_t* opnd_off;
+  uint32_t* opnd;
+  int32_t* str_off;
+  uint8_t* chars;
+  int64_t* rec_mod_off;
+  // workspace
+  uint32_t* ctrl;               // 0, 1: scan claims; 2: a scan gave up waiting
+  unsigned long long* mscan;    // per module: record count, then its exclusive scan
+  unsigned long long* mstate;   // look-back states of the module scan
+  unsigned long long* rscan;    // per record: packed counts, then their exclusive scan
+  unsigned long long* rstate;   // look-back states of the record scan
+};
+
+struct RLayout {
+  size_t ctrl, mscan, mstate, rscan, rstate, total;
+};
+
+inline RLayout make_rlayout(int64_t n_modules, int64_t n_words) {
+  RLayout L;
+  size_t off = 0;
+  L.ctrl = off;
+  off = align256(off + 256);
+  L.mscan = off;
+  off = align256(off + 8 * size_t(n_modules + 1));
+  L.mstate = off;
+  off = align256(off + 128 * size_t((n_modules + 1) / 1024 + 2));
+  L.rscan = off;
+  off = align256(off + 8 * size_t(n_words + 1));
+  L.rstate = off;
+  off = align256(off + 128 * size_t((n_words + 1) / 1024 + 2));
+  L.total = off;
+  return L;
+}
+
+void launch_records(const RParams& p, hipStream_t s);
+
 }  // namespace spv

@@ -1,0 +1,267 @@
+// Decode's records mode for gfx950: the instructions that decode found,
+// turned back into the encoder's record layout (opcode, non-string operand
+// words, string bytes), so that encoding the records of a valid module gives
+// its words again.
+//
+// What is computed (Beehive SPIR-V Toolkit paper, arXiv 2305.09493): the
+// disassembler's instruction view of a binary (section "Dis/Assembler") in the
+// form the library's writer takes (section "SPIR-V Library"; operand words
+// and strings as in section "Parsing Operand Kinds").  Module m contributes
+// the records of its valid instruction prefix: results[m].n_inst records,
+// or none when its header check failed.
+//
+// How: one scan over the modules gives each module's first record; a count
+// pass gives every record's operand and character counts (an OpName string
+// was validated by decode, so its length follows from its last word alone);
+// one scan of the packed counts gives both offset arrays; a scatter writes
+// the records.  The scans are single-pass: blocks of 1024 values, claimed in
+// order, chained by a decoupled look-back.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "spv_internal.h"
+
+namespace spv {
+
+namespace {
+
+constexpr int kRecThreads = 256;
+constexpr int kScanPerThread = 4;
+constexpr int kScanBlock = kRecThreads * kScanPerThread;  // values per scan block
+constexpr int kRStateStride = 16;                          // one 128-byte line per block state
+constexpr unsigned long long kRAgg = 1ull << 62, kRIncl = 2ull << 62, kRMask = 3ull << 62;
+constexpr unsigned long long kRSum = (1ull << 62) - 1;
+
+__device__ __forceinline__ unsigned long long ld_state_r(const unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_state_r(unsigned long long* p, unsigned long long v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Module of global record r: the last m with rec_mod_off[m] <= r among the
+// modules with records (binary search; rec_mod_off is non-decreasing).
+__device__ __forceinline__ int64_t rec_module(const int64_t* rec_mod_off, int64_t M, int64_t r) {
+  int64_t lo = 0, hi = M - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (rec_mod_off[mid] <= r) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// A record's instruction: its first word's position and the word.
+struct RecInst {
+  int64_t pos;
+  uint32_t w0;
+};
+
+__device__ __forceinline__ RecInst rec_inst(const RParams& P, int64_t r) {
+  const int64_t m = rec_module(P.rec_mod_off, P.M, r);
+  const int64_t j = r - P.rec_mod_off[m];
+  const int64_t base = P.mod_off[m];
+  RecInst ri;
+  ri.pos = base + int64_t(P.idx_off[base + j]);
+  ri.w0 = P.words[ri.pos];
+  return ri;
+}
+
+// Operand words and string bytes of a record.  OpName: one operand (its
+// target) and the string, whose first NUL lies in its last word (decode
+// checked that), so its length is 4 * (string words - 1) plus the bytes of
+// the last word before the NUL.
+__device__ __forceinline__ void rec_counts(const RParams& P, const RecInst& ri, uint32_t& n_opnd, uint32_t& n_chars) {
+  const uint32_t wc = ri.w0 >> 16, op = ri.w0 & 0xFFFFu;
+  if (op == uint32_t(kOpName)) {
+    const uint32_t last = P.words[ri.pos + wc - 1];
+    uint32_t k = 0;
+    while (k < 4 && ((last >> (8 * k)) & 0xFFu) != 0) ++k;
+    n_opnd = 1;
+    n_chars = 4 * (wc - 3) + k;
+  } else {
+    n_opnd = wc - 1;
+    n_chars = 0;
+  }
+}
+
+// Single-pass exclusive scan of n 64-bit values (in may alias out): out[i] =
+// sum of in[0 .. i), out[n] = the total.  Blocks claim their chunk from
+// ctrl[claim]; states[] (kRStateStride words per block) must be zero.
+__device__ void scan_block(const unsigned long long* in, int64_t n, unsigned long long* out,
+                           unsigned long long* states, uint32_t* claim, uint32_t* spin_err) {
+  __shared__ uint32_t s_bid;
+  __shared__ unsigned long long s_w[kRecThreads / 64];
+  __shared__ unsigned long long s_pre;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid == 0) s_bid = atomicAdd(claim, 1u);
+  __syncthreads();
+  const long long b = s_bid;
+  const int64_t i0 = int64_t(b) * kScanBlock + int64_t(tid) * kScanPerThread;
+  unsigned long long v[kScanPerThread], t = 0;
+#pragma unroll
+  for (int k = 0; k < kScanPerThread; ++k) {
+    v[k] = (i0 + k < n) ? in[i0 + k] : 0ull;
+    t += v[k];
+  }
+  unsigned long long inc = t;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const unsigned long long u = __shfl_up(inc, d);
+    if (lane >= d) inc += u;
+  }
+  if (lane == 63) s_w[wave] = inc;
+  __syncthreads();
+  unsigned long long wpre = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < kRecThreads / 64; ++w) {
+    if (w < wave) wpre += s_w[w];
+    tot += s_w[w];
+  }
+  if (tid == 64) st_state_r(&states[b * kRStateStride], kRAgg | tot);
+  if (wave == 0) {
+    unsigned long long prefix = 0;
+    long long hi = b - 1;
+    uint32_t spins = 0;
+    while (hi >= 0) {
+      const long long u = hi - lane;
+      const unsigned long long st = (u >= 0) ? ld_state_r(&states[u * kRStateStride]) : kRIncl;
+      const unsigned long long f = st & kRMask;
+      const uint64_t stopm = __ballot(f == kRIncl);
+      const uint64_t unpub = __ballot(f == 0);
+      const int sl = stopm ? int(__builtin_ctzll(stopm)) : 64;
+      const uint64_t need = (sl >= 63) ? ~0ull : ((2ull << sl) - 1ull);
+      if (unpub & need) {
+        if (++spins > kSpinLimit) {
+          if (lane == 0) atomicOr(spin_err, 1u);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        continue;
+      }
+      unsigned long long c = (lane <= sl) ? (st & kRSum) : 0ull;
+#pragma unroll
+      for (int d = 32; d >= 1; d >>= 1) c += __shfl_xor(c, d);
+      prefix += c;
+      if (sl < 64) break;
+      hi -= 64;
+    }
+    if (lane == 0) {
+      st_state_r(&states[b * kRStateStride], kRIncl | (prefix + tot));
+      s_pre = prefix;
+    }
+  }
+  __syncthreads();
+  unsigned long long run = s_pre + wpre + (inc - t);
+#pragma unroll
+  for (int k = 0; k < kScanPerThread; ++k) {
+    if (i0 + k < n) out[i0 + k] = run;
+    run += v[k];
+  }
+  // the total, after the last value
+  if (i0 <= n && n < i0 + kScanPerThread) out[n] = run;
+}
+
+}  // namespace
+
+// Clears the scan states and claim counters; per module, its record count.
+__global__ __launch_bounds__(kRecThreads) void k_rec_init(RParams P) {
+  const int64_t gtid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t nth = int64_t(gridDim.x) * blockDim.x;
+  if (gtid < 4) P.ctrl[gtid] = 0;
+  const int64_t ns = (P.M + 1) / kScanBlock + 2, nr = (P.cap_records + 1) / kScanBlock + 2;
+  for (int64_t i = gtid; i < ns; i += nth) P.mstate[i * kRStateStride] = 0;
+  for (int64_t i = gtid; i < nr; i += nth) P.rstate[i * kRStateStride] = 0;
+  for (int64_t m = gtid; m < P.M; m += nth) {
+    const spv_result r = P.results[m];
+    const bool hdr_ok = r.code == SPV_OK || (r.code >= SPV_E_BAD_WORD_COUNT && r.code <= SPV_E_UNDEFINED_ID);
+    P.mscan[m] = hdr_ok ? (unsigned long long)r.n_inst : 0ull;
+  }
+}
+
+// rec_mod_off = exclusive scan of the module record counts.
+__global__ __launch_bounds__(kRecThreads) void k_rec_modscan(RParams P) {
+  scan_block(P.mscan, P.M, P.mscan, P.mstate, &P.ctrl[0], &P.ctrl[2]);
+}
+
+// Packed counts of every record: operand words << 32 | string bytes.
+__global__ __launch_bounds__(kRecThreads) void k_rec_count(RParams P) {
+  const int64_t gtid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t nth = int64_t(gridDim.x) * blockDim.x;
+  if (P.ctrl[2]) return;  // the module scan gave up: rec_mod_off is not valid
+  // (rec_mod_off is the module scan, copied out by k_rec_offsets)
+  const int64_t N = min(P.rec_mod_off[P.M], P.cap_records);
+  for (int64_t r = gtid; r < N; r += nth) {
+    const RecInst ri = rec_inst(P, r);
+    uint32_t no, nc;
+    rec_counts(P, ri, no, nc);
+    P.rscan[r] = ((unsigned long long)no << 32) | nc;
+  }
+}
+
+// rec_mod_off (int64) from the module scan.
+__global__ __launch_bounds__(kRecThreads) void k_rec_offsets(RParams P) {
+  const int64_t gtid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t nth = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t m = gtid; m <= P.M; m += nth) P.rec_mod_off[m] = int64_t(P.mscan[m]);
+}
+
+// Exclusive scan of the packed record counts (both halves at once: neither
+// half's total reaches 2^32).
+__global__ __launch_bounds__(kRecThreads) void k_rec_scan(RParams P) {
+  if (P.ctrl[2]) return;
+  const int64_t N = min(P.rec_mod_off[P.M], P.cap_records);
+  if (int64_t(blockIdx.x) * kScanBlock > N) return;  // (the grid is sized for the largest N)
+  scan_block(P.rscan, N, P.rscan, P.rstate, &P.ctrl[1], &P.ctrl[2]);
+}
+
+// Records: opcode, offsets, operand words, string bytes.
+__global__ __launch_bounds__(kRecThreads) void k_rec_scatter(RParams P) {
+  const int64_t gtid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t nth = int64_t(gridDim.x) * blockDim.x;
+  if (P.ctrl[2]) {  // a scan gave up waiting: no valid output
+    for (int64_t m = gtid; m <= P.M; m += nth) P.rec_mod_off[m] = -1;
+    return;
+  }
+  const int64_t N = min(P.rec_mod_off[P.M], P.cap_records);
+  for (int64_t r = gtid; r <= N; r += nth) {
+    const unsigned long long x = P.rscan[r];
+    const int32_t oo = int32_t(x >> 32), so = int32_t(x & 0xFFFFFFFFull);
+    P.opnd_off[r] = oo;
+    P.str_off[r] = so;
+    if (r == N) break;
+    const RecInst ri = rec_inst(P, r);
+    const uint32_t wc = ri.w0 >> 16, op = ri.w0 & 0xFFFFu;
+    P.op[r] = uint16_t(op);
+    if (op == uint32_t(kOpName)) {
+      P.opnd[oo] = P.words[ri.pos + 1];
+      uint32_t no, nc;
+      rec_counts(P, ri, no, nc);
+      for (uint32_t k = 0; k < nc; k += 4) {
+        const uint32_t w = P.words[ri.pos + 2 + k / 4];
+#pragma unroll
+        for (uint32_t q = 0; q < 4; ++q)
+          if (k + q < nc) P.chars[so + k + q] = uint8_t(w >> (8 * q));
+      }
+    } else {
+      for (uint32_t i = 1; i < wc; ++i) P.opnd[oo + i - 1] = P.words[ri.pos + i];
+    }
+  }
+}
+
+int records_grid(int64_t n) {
+  const int64_t g = n / kRecThreads + 1;
+  return int(g > 4096 ? 4096 : g);
+}
+
+void launch_records(const RParams& p, hipStream_t s) {
+  hipLaunchKernelGGL(k_rec_init, dim3(records_grid(p.M > p.cap_records / kScanBlock ? p.M : p.cap_records / kScanBlock)),
+                     dim3(kRecThreads), 0, s, p);
+  hipLaunchKernelGGL(k_rec_modscan, dim3(int(p.M / kScanBlock + 1)), dim3(kRecThreads), 0, s, p);
+  hipLaunchKernelGGL(k_rec_offsets, dim3(records_grid(p.M + 1)), dim3(kRecThreads), 0, s, p);
+  hipLaunchKernelGGL(k_rec_count, dim3(records_grid(p.cap_records)), dim3(kRecThreads), 0, s, p);
+  hipLaunchKernelGGL(k_rec_scan, dim3(int(p.cap_records / kScanBlock + 1)), dim3(kRecThreads), 0, s, p);
+  hipLaunchKernelGGL(k_rec_scatter, dim3(records_grid(p.cap_records + 1)), dim3(kRecThreads), 0, s, p);
+}
+
+}  // namespace spv
