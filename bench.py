@@ -117,6 +117,29 @@ def encode_leg(ctx, dev, steps=10):
             "hbm_frac": bytes_moved / dt / 1e9 / HBM_PEAK_GBS, "output_matches_generator": words_out == expect}
 
 
+def records_leg(ctx, words, mod_off, idx_off, res, W, steps=10):
+    """Decode's records mode on the timed module: records of its 16M
+    instructions from the index of the timed call; records/s and the
+    algorithmic bytes (words and index read, records written) per second."""
+    import torch
+
+    import paper_2305_09493_amd as spv
+    rec = spv.decode_records(words, mod_off, idx_off, res, ctx=ctx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        rec = spv.decode_records(words, mod_off, idx_off, res, ctx=ctx)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    n = int(rec["rec_mod_off"][-1].item())
+    n_opnd = int(rec["opnd_off"][n].item())
+    n_chars = int(rec["str_off"][n].item())
+    bytes_moved = 4 * W + 4 * n + (2 * n + 8 * (n + 1) + 4 * n_opnd + n_chars)
+    return {"records": n, "operand_words": n_opnd, "string_bytes": n_chars, "ms_per_call": 1e3 * dt,
+            "records_per_s": n / dt, "algorithmic_GBps": bytes_moved / dt / 1e9,
+            "hbm_frac": bytes_moved / dt / 1e9 / HBM_PEAK_GBS}
+
+
 def serve_leg(args):
     """Poisson stream of validate requests: continuous batching vs one module
     per launch, same streams, kernels and arrival trace."""
@@ -153,6 +176,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--cache", default=None, help="npy file to keep the generated module between runs")
     ap.add_argument("--encode", action="store_true", help="add the encode leg (10M records, 1024 modules)")
+    ap.add_argument("--records", action="store_true", help="add the records-mode leg (records of the timed module)")
     ap.add_argument("--serve", action="store_true", help="add the serving leg (Poisson stream, batched vs "
                                                          "one module per launch)")
     ap.add_argument("--serve-rates", default="20000", help="comma-separated arrival rates for --serve")
@@ -279,6 +303,7 @@ def main():
                    "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                    "modules_flagged": faults, "launches": n_rep}
 
+    records = records_leg(ctx, words, mod_off, idx_off, res, W) if args.records else None
     encode = encode_leg(ctx, dev) if args.encode else None
     serving = serve_leg(args) if args.serve else None
 
@@ -309,6 +334,8 @@ def main():
         "batched": batched,
         "parity_checked": checked,
     }
+    if records is not None:
+        line["records"] = records
     if encode is not None:
         line["encode"] = encode
     if serving is not None:

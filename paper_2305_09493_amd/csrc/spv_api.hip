@@ -334,6 +334,7 @@ int spv_decode_records(spv_ctx* ctx, const uint32_t* words, const int64_t* mod_o
   p.mscan = reinterpret_cast<unsigned long long*>(base + L.mscan);
   p.mstate = reinterpret_cast<unsigned long long*>(base + L.mstate);
   p.rscan = reinterpret_cast<unsigned long long*>(base + L.rscan);
+  p.btot = reinterpret_cast<unsigned long long*>(base + L.btot);
   p.rstate = reinterpret_cast<unsigned long long*>(base + L.rstate);
   spv::launch_records(p, static_cast<hipStream_t>(stream));
   return check_launch(ctx);

@@ -266,12 +266,13 @@ struct RParams {
   uint32_t* ctrl;               // 0, 1: scan claims; 2: a scan gave up waiting
   unsigned long long* mscan;    // per module: record count, then its exclusive scan
   unsigned long long* mstate;   // look-back states of the module scan
-  unsigned long long* rscan;    // per record: packed counts, then their exclusive scan
-  unsigned long long* rstate;   // look-back states of the record scan
+  unsigned long long* rscan;    // per record: packed counts (operand words << 32 | string bytes)
+  unsigned long long* btot;     // per block of 1024 records: packed total, then its exclusive scan
+  unsigned long long* rstate;   // look-back states of the block-total scan
 };
 
 struct RLayout {
-  size_t ctrl, mscan, mstate, rscan, rstate, total;
+  size_t ctrl, mscan, mstate, rscan, btot, rstate, total;
 };
 
 inline RLayout make_rlayout(int64_t n_modules, int64_t n_words) {
@@ -285,8 +286,11 @@ inline RLayout make_rlayout(int64_t n_modules, int64_t n_words) {
   off = align256(off + 128 * size_t((n_modules + 1) / 1024 + 2));
   L.rscan = off;
   off = align256(off + 8 * size_t(n_words + 1));
+  const int64_t nb = n_words / 1024 + 1;  // blocks of 1024 records, at most
+  L.btot = off;
+  off = align256(off + 8 * size_t(nb + 1));
   L.rstate = off;
-  off = align256(off + 128 * size_t((n_words + 1) / 1024 + 2));
+  off = align256(off + 128 * size_t(nb / 1024 + 2));
   L.total = off;
   return L;
 }
