@@ -2,8 +2,8 @@
 benchmark times (the context's default tuning):
   * the batched workload: 4096 lognormal modules (about 56M words) with 41
     injected faults; every result field and every module's index prefix
-    against the oracle, and each faulted module against the code its fault
-    was built to produce;
+    against the oracle, each faulted module against the code its fault was
+    built to produce, and decode's records of the whole batch;
   * the encode workload: 10M records in 1024 modules; every output word,
     offset and status against the oracle.
 (The single 16M-instruction module is checked against the oracle by
@@ -28,6 +28,26 @@ def test_full_batched_workload_parity():
         e = b.modules[m].expect
         assert tuple(int(x) for x in res[m]) == (e["code"], e["sem_mask"], e["err_word"], e["n_inst"]), m
     assert int(np.sum(res[:, 0] != 0)) == 41
+    # decode's records mode on the same batch (faulted modules keep their
+    # valid prefix)
+    import torch
+
+    import paper_2305_09493_amd as spv
+    from gpu_util import to_dev
+    w, mo = to_dev(b.words, b.mod_off)
+    gres, gio, _ = spv.validate(w, mo)
+    rec = spv.decode_records(w, mo, gio, gres)
+    torch.cuda.synchronize()
+    o = oracle.records(b.words, b.mod_off)
+    rmo = rec["rec_mod_off"].cpu().numpy()
+    n = int(rmo[-1])
+    assert np.array_equal(rmo, o["rec_mod_off"])
+    assert np.array_equal(rec["op"].cpu().numpy().view(np.uint16)[:n], o["op"])
+    oo = rec["opnd_off"].cpu().numpy()[:n + 1]
+    so = rec["str_off"].cpu().numpy()[:n + 1]
+    assert np.array_equal(oo, o["opnd_off"]) and np.array_equal(so, o["str_off"])
+    assert np.array_equal(rec["opnd"].cpu().numpy().view(np.uint32)[:oo[-1]], o["opnd"])
+    assert np.array_equal(rec["chars"].cpu().numpy()[:so[-1]], o["chars"])
 
 
 def test_full_encode_workload_parity():
