@@ -155,3 +155,21 @@ def test_repeat_runs_identical():
     r1 = compare(b.words, b.mod_off, label="repeat 1")
     r2 = compare(b.words, b.mod_off, label="repeat 2")
     assert np.array_equal(r1, r2)
+
+
+def test_real_modules_mixed_with_generated():
+    """Real SPIR-V modules built here (hipcc, generic SPIR-V target) between
+    generated ones: the chain pass analyses every tile of the real binaries;
+    results and index prefixes must equal the oracle's."""
+    import realspv
+    if not realspv.available():
+        pytest.skip("hipcc / clang-offload-bundler not available")
+    real = [realspv.module(n) for n in sorted(realspv.SOURCES)]
+    gen = [spvgen.gen_module([33, i], n).words for i, n in enumerate([3000, 700])]
+    mods = [real[0], gen[0], real[1], gen[1], real[0]]
+    words = np.concatenate(mods).astype(np.uint32)
+    mod_off = np.concatenate([[0], np.cumsum([m.size for m in mods])]).astype(np.int64)
+    compare(words, mod_off, label="real + generated")
+    compare(words, mod_off, semantic=False, label="real + generated, decode")
+    for m in real:
+        compare(m, [0, m.size], label=f"real module alone ({m.size} words)")
