@@ -118,26 +118,6 @@ __device__ __forceinline__ bool string_ok_global(const uint32_t* w, int64_t n_wo
   return (x >> (8 * k)) == 0;
 }
 
-// Same rule for a string of at most 12 words (instructions of the fast
-// path): every load is issued before any test.
-__device__ __forceinline__ bool string_ok_short(const uint32_t* w, int n_words) {
-  uint32_t x[12];
-#pragma unroll
-  for (int i = 0; i < 12; ++i) x[i] = (i < n_words) ? w[i] : 0u;
-  bool ok = true;
-  uint32_t last = 0;
-#pragma unroll
-  for (int i = 0; i < 12; ++i) {
-    uint32_t z = (x[i] - 0x01010101u) & ~x[i] & 0x80808080u;
-    if (i + 1 < n_words) ok = ok && z == 0;
-    if (i + 1 == n_words) last = x[i];
-  }
-  uint32_t z = (last - 0x01010101u) & ~last & 0x80808080u;
-  if (z == 0) return false;
-  int k = __builtin_ctz(z) >> 3;
-  return ok && (last >> (8 * k)) == 0;
-}
-
 // Exact parse-stage code of a candidate start (0 if it is a valid
 // instruction).  end = end of its module (absolute word index).
 __device__ __forceinline__ uint32_t start_code(const uint32_t* words, const uint32_t* tbl, int64_t pos, int64_t end) {
