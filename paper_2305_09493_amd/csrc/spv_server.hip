@@ -26,6 +26,7 @@
 #include <utility>
 #include <vector>
 
+#include "spv_admission.h"
 #include "spv_internal.h"
 
 namespace {
@@ -84,13 +85,7 @@ int64_t now_ns(const spv_server* s) {
   return std::chrono::duration_cast<std::chrono::nanoseconds>(Clock::now() - s->t0).count();
 }
 
-int64_t bucket_up(int64_t x) {
-  // round up to a multiple of 2^(floor(log2 x) - 3): at most 12.5% padding
-  if (x <= 64) return 64;
-  int lg = 63 - __builtin_clzll(uint64_t(x));
-  int64_t step = int64_t(1) << (lg - 3);
-  return (x + step - 1) / step * step;
-}
+using spv::bucket_up;
 
 // Launch (or replay) the validation of the slot's staged batch.
 hipError_t launch_batch(spv_server* S, Slot& sl, int64_t M, int64_t W) {
@@ -143,6 +138,7 @@ void worker_main(spv_server* S) {
   (void)hipSetDevice(S->device);
   std::deque<Req> ready;      // arrived, waiting for a slot (FIFO)
   std::deque<Req> waiting;    // submitted, not yet arrived
+  std::vector<uint8_t> action;  // admission decisions for the front of `ready`
   for (;;) {
     {
       std::lock_guard<std::mutex> lk(S->mu);
@@ -186,9 +182,14 @@ void worker_main(spv_server* S) {
       if (sl.busy || ready.empty()) continue;
       int64_t W = 0, M = 0;
       sl.h_mod_off[0] = 0;
-      while (!ready.empty() && M < S->max_batch && M + 2 <= sl.cap_modules) {
+      const int64_t n_look = int64_t(ready.size()) < S->max_batch + 64 ? int64_t(ready.size()) : S->max_batch + 64;
+      action.resize(size_t(n_look));
+      const int64_t n_ex = spv::admit_batch(
+          n_look, [&](int64_t i) { return ready[size_t(i)].n; }, S->max_batch, sl.cap_modules, sl.cap_words,
+          action.data());
+      for (int64_t i = 0; i < n_ex; ++i) {
         const Req& r = ready.front();
-        if (r.n > sl.cap_words - 1) {
+        if (action[size_t(i)] == spv::kAdmitReject) {
           // larger than a slot: rejected
           std::lock_guard<std::mutex> lk(S->mu);
           spv_completion c;
@@ -199,14 +200,12 @@ void worker_main(spv_server* S) {
           c.t_done_ns = now_ns(S);
           S->completed.push_back(c);
           S->in_flight -= 1;
-          ready.pop_front();
-          continue;
+        } else {
+          memcpy(sl.h_words + W, r.words, size_t(r.n) * 4);
+          W += r.n;
+          sl.batch.push_back(r);
+          sl.h_mod_off[++M] = W;
         }
-        if (W + r.n > sl.cap_words - 1) break;
-        memcpy(sl.h_words + W, r.words, size_t(r.n) * 4);
-        W += r.n;
-        sl.batch.push_back(r);
-        sl.h_mod_off[++M] = W;
         ready.pop_front();
       }
       if (M == 0) continue;
