@@ -43,6 +43,7 @@ extern "C" {
 #define SPV_ERR_WORKSPACE (-3)   /* ws too small (see spv_workspace_size) or null */
 #define SPV_ERR_HIP (-4)         /* a HIP runtime call failed; see spv_last_hip_error */
 #define SPV_ERR_LIMIT (-5)       /* a module has >= 2^32 words, or too many modules */
+#define SPV_ERR_CANCELED (-6)    /* (server completion status) the request was cancelled before a batch took it */
 
 /* ---- per-module result codes (decode / validate) ------------------------
  * Checks run in stages; the first failing stage decides the code.
@@ -241,7 +242,7 @@ typedef struct spv_server spv_server;
 typedef struct {
   int64_t id;            /* caller's request id */
   spv_result result;     /* the module's validation result */
-  int32_t status;        /* SPV_SUCCESS, SPV_ERR_CAPACITY or SPV_ERR_HIP */
+  int32_t status;        /* SPV_SUCCESS, SPV_ERR_CAPACITY, SPV_ERR_CANCELED or SPV_ERR_HIP */
   int32_t pad;
   int64_t t_arrival_ns;  /* arrival time */
   int64_t t_done_ns;     /* time the worker saw the batch complete */
@@ -257,6 +258,11 @@ int spv_server_start(spv_server *srv);
 int spv_server_submit(spv_server *srv, int64_t n, const int64_t *ids, const uint32_t *const *words,
                       const int64_t *n_words, const int64_t *t_arrival_ns);
 /* Move up to max_out completions to out; *pending = submitted, not completed. */
+/* Cancel queued requests by id: every listed request that no batch has taken
+ * yet completes with status SPV_ERR_CANCELED (and a zero result) at the
+ * worker's next step; ids of requests already in a batch, done or unknown
+ * are ignored.  Cancels apply to requests submitted before the call. */
+int spv_server_cancel(spv_server *srv, int64_t n, const int64_t *ids);
 int spv_server_poll(spv_server *srv, spv_completion *out, int64_t max_out, int64_t *n_out, int64_t *pending);
 int spv_server_stats(spv_server *srv, int64_t *n_batches, int64_t *n_modules, int64_t *n_words, int64_t *max_batch,
                      int64_t *slot_capacity_words);

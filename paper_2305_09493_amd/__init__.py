@@ -21,7 +21,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libspvgpu.so")
 
 SPV_SUCCESS = 0
-ERRORS = {-1: "invalid argument", -2: "capacity", -3: "workspace", -4: "HIP error", -5: "limit"}
+ERRORS = {-1: "invalid argument", -2: "capacity", -3: "workspace", -4: "HIP error", -5: "limit", -6: "canceled"}
 
 OK, E_TRUNCATED_HEADER, E_BAD_MAGIC, E_BAD_VERSION, E_BAD_SCHEMA = 0, 1, 2, 3, 4
 E_BAD_WORD_COUNT, E_UNKNOWN_OPCODE, E_BAD_STRING = 5, 6, 7
@@ -67,7 +67,7 @@ def load_library():
         for name in ("spv_create", "spv_destroy", "spv_set_tuning", "spv_workspace_size", "spv_decode",
                      "spv_validate", "spv_encode_bound", "spv_encode_workspace_size", "spv_encode",
                      "spv_set_timing", "spv_read_timing", "spv_get_tuning", "spv_server_create", "spv_server_start", "spv_server_submit",
-           "spv_server_poll", "spv_server_stats", "spv_server_destroy"):
+           "spv_server_poll", "spv_server_stats", "spv_server_destroy", "spv_server_cancel"):
             getattr(lib, name).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -77,7 +77,7 @@ EXPORTS = ("spv_create", "spv_destroy", "spv_last_hip_error", "spv_set_tuning", 
            "spv_decode", "spv_validate", "spv_encode_bound", "spv_encode_workspace_size", "spv_encode",
            "spv_records_workspace_size", "spv_decode_records",
            "spv_set_timing", "spv_read_timing", "spv_get_tuning", "spv_server_create", "spv_server_start", "spv_server_submit",
-           "spv_server_poll", "spv_server_stats", "spv_server_destroy")
+           "spv_server_poll", "spv_server_stats", "spv_server_destroy", "spv_server_cancel")
 
 
 def _torch():

@@ -23,6 +23,7 @@
 #include <map>
 #include <mutex>
 #include <thread>
+#include <unordered_set>
 #include <utility>
 #include <vector>
 
@@ -69,6 +70,7 @@ struct spv_server {
   bool use_graphs = false;
   std::mutex mu;
   std::deque<Req> incoming;  // submitted, sorted by arrival within each submit call
+  std::unordered_set<int64_t> cancel;  // ids to cancel if not yet admitted to a batch
   std::vector<spv_completion> completed;
   std::thread worker;
   std::atomic<bool> stop{false};
@@ -140,11 +142,41 @@ void worker_main(spv_server* S) {
   std::deque<Req> waiting;    // submitted, not yet arrived
   std::vector<uint8_t> action;  // admission decisions for the front of `ready`
   for (;;) {
+    std::unordered_set<int64_t> to_cancel;
     {
       std::lock_guard<std::mutex> lk(S->mu);
       while (!S->incoming.empty()) {
         waiting.push_back(S->incoming.front());
         S->incoming.pop_front();
+      }
+      to_cancel.swap(S->cancel);
+    }
+    if (!to_cancel.empty()) {
+      // cancelled requests not yet in a batch complete at once; ids not
+      // queued any more (admitted or done) are ignored
+      const int64_t t = now_ns(S);
+      std::vector<spv_completion> done;
+      for (std::deque<Req>* q : {&waiting, &ready}) {
+        std::deque<Req> keep;
+        for (const Req& r : *q) {
+          if (to_cancel.count(r.id)) {
+            spv_completion c;
+            memset(&c, 0, sizeof(c));
+            c.id = r.id;
+            c.status = SPV_ERR_CANCELED;
+            c.t_arrival_ns = r.t_arr_ns;
+            c.t_done_ns = t;
+            done.push_back(c);
+          } else {
+            keep.push_back(r);
+          }
+        }
+        q->swap(keep);
+      }
+      if (!done.empty()) {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->completed.insert(S->completed.end(), done.begin(), done.end());
+        S->in_flight -= int64_t(done.size());
       }
     }
     const int64_t now = now_ns(S);
@@ -329,6 +361,13 @@ int spv_server_submit(spv_server* S, int64_t n, const int64_t* ids, const uint32
     S->incoming.push_back(r);
   }
   S->in_flight += n;
+  return SPV_SUCCESS;
+}
+
+int spv_server_cancel(spv_server* S, int64_t n, const int64_t* ids) {
+  if (!S || n < 0 || (n > 0 && !ids)) return SPV_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(S->mu);
+  for (int64_t i = 0; i < n; ++i) S->cancel.insert(ids[i]);
   return SPV_SUCCESS;
 }
 

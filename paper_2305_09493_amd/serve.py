@@ -39,8 +39,9 @@ def _bind(lib):
     lib.spv_server_poll.argtypes = [P, P, I64, ctypes.POINTER(I64), ctypes.POINTER(I64)]
     lib.spv_server_stats.argtypes = [P] + [ctypes.POINTER(I64)] * 5
     lib.spv_server_destroy.argtypes = [P]
+    lib.spv_server_cancel.argtypes = [P, I64, P]
     for n in ("spv_server_create", "spv_server_start", "spv_server_submit", "spv_server_poll",
-              "spv_server_stats", "spv_server_destroy"):
+              "spv_server_stats", "spv_server_destroy", "spv_server_cancel"):
         getattr(lib, n).restype = ctypes.c_int
     lib._spv_server_bound = True
     return lib
@@ -85,6 +86,14 @@ class Server:
         if rc != SPV_SUCCESS:
             raise SpvError(f"spv_server_submit failed: {ERRORS.get(rc, rc)}")
         self._keep.extend([ptrs, sizes, ids] + ([] if tarr is None else [tarr]))
+
+    def cancel(self, ids):
+        """Cancel queued requests (those no batch has taken yet complete with
+        status SPV_ERR_CANCELED)."""
+        ids = np.ascontiguousarray(ids, dtype=np.int64)
+        rc = self.lib.spv_server_cancel(self.h, ids.size, ids.ctypes.data)
+        if rc != SPV_SUCCESS:
+            raise SpvError(f"spv_server_cancel failed: {ERRORS.get(rc, rc)}")
 
     def poll(self, max_out: int = 65536):
         buf = np.zeros(max_out, dtype=COMPLETION_DTYPE)

@@ -70,3 +70,25 @@ def test_oversized_request_rejected():
     comp = comp[np.argsort(comp["id"])]
     assert list(comp["status"]) == [0, -2, 0]
     assert comp["code"][0] == 0 and comp["n_inst"][0] == 50
+
+
+def test_cancelled_requests_complete_with_their_status():
+    """Requests cancelled before a batch takes them complete with
+    SPV_ERR_CANCELED and a zero result; the others are validated as usual."""
+    from paper_2305_09493_amd.serve import Server
+    mods = _pool()[:60]
+    exp = _expected(mods)
+    n = len(mods)
+    with Server(max_batch_modules=4096, n_slots=2) as srv:
+        srv.submit(mods, ids=np.arange(n), t_arrival_s=np.full(n, 0.3))  # arrive after the cancel
+        cancel = np.arange(0, n, 3)
+        srv.cancel(np.concatenate([cancel, [10_000]]))  # an unknown id is ignored
+        srv.start()
+        comp = srv.drain(timeout_s=60)
+    comp = comp[np.argsort(comp["id"])]
+    assert comp.size == n and np.array_equal(comp["id"], np.arange(n))
+    is_c = np.isin(comp["id"], cancel)
+    assert np.all(comp["status"][is_c] == -6) and np.all(comp["code"][is_c] == 0)
+    assert np.all(comp["status"][~is_c] == 0)
+    got = np.stack([comp[k] for k in ("code", "sem_mask", "err_word", "n_inst")], axis=1).astype(np.uint32)
+    assert np.array_equal(got[~is_c], exp[~is_c])
