@@ -5,18 +5,20 @@ Workload (timed): one synthetic module of 16M instructions (about 65M uint32
 words, 260 MB) from the seeded generator (seed 2), decoded and validated with
 the instruction index written - one step is one spv_validate call over the
 whole module (header, boundary recovery, parse checks, index, result-ID
-checks).  Inputs are resident in HBM before timing starts.
+checks), replayed from a HIP graph captured once (every kernel runs in every
+step; --eager launches each call instead).  Inputs are resident in HBM
+before timing starts.
 
 Also reported on the same JSON line:
   roofline      the decode/validate path's algorithmic bytes per call (4 B
                 per word read + 6 B per index entry written) over the
-                average duration of its kernels - chain pass, resolve pass,
-                resolved walk, and the single-pass walk, which returns at
-                once when the walk is resolved - measured with HIP events
-                around them on the library's stream, against 8 TB/s;
-                traffic: HBM bytes per call of those kernels from the
+                average duration of a whole validate call, timed with two
+                HIP events around the K replays of the captured call on its
+                stream (--eager: eager calls, the library's events around
+                the chain pass, resolve pass, resolved walk and single-pass
+                walk), against 8 TB/s; traffic: HBM bytes per call from the
                 committed rocprofv3 counter summary, when it was taken on
-                the current kernel source;
+                the current kernel code;
   cpu_baseline  the CPU oracle (single thread) on the same module;
   batched       4096 lognormal modules with 41 injected faults per launch:
                 words/s and p50 / p99 per-launch latency.
@@ -170,6 +172,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n-inst", type=int, default=16_000_000)
+    ap.add_argument("--eager", action="store_true",
+                    help="time eager calls (library events around the walk kernels) instead of graph replays")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched latency leg")
     ap.add_argument("--no-check", action="store_true", help="skip the full-size parity check")
@@ -225,30 +229,59 @@ def main():
     ws = torch.empty(ctx.workspace_size(1, W), dtype=torch.uint8, device=dev)
     out = (res, idx_off, idx_op)
 
-    def step():
-        spv.validate(words, mod_off, ctx=ctx, out=out, workspace=ws)
+    def step(stream=None):
+        spv.validate(words, mod_off, ctx=ctx, out=out, workspace=ws, stream=stream)
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
 
-    # timed region: K whole-path steps
-    ctx.set_timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    k_ms, k_n = ctx.read_timing()
-    ctx.set_timing(False)
+    algo_bytes = 4.0 * W + 6.0 * n_inst
+    if args.eager:
+        # timed region: K whole-path calls; the library's events time its
+        # boundary-recovery and walk kernels in each call
+        ctx.set_timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        k_ms, k_n = ctx.read_timing()
+        ctx.set_timing(False)
+        k_avg_s = (k_ms / k_n) / 1e3
+        timed_kernels = "k_chain + k_resolve + k_walk (+ k_main, returns at once)"
+    else:
+        # timed region: K replays of one captured validate call (every kernel
+        # of the call runs in every replay), between two HIP events on the
+        # stream the replays run on
+        graph = torch.cuda.CUDAGraph()
+        gs = torch.cuda.Stream()
+        with torch.cuda.stream(gs):
+            with torch.cuda.graph(graph, stream=gs):
+                step(gs)
+        torch.cuda.synchronize()
+        for _ in range(args.warmup):
+            graph.replay()
+        torch.cuda.synchronize()
+        # (replay() launches the graph on the current stream: the events go there)
+        rs = torch.cuda.current_stream()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        ev0.record(rs)
+        for _ in range(args.steps):
+            graph.replay()
+        ev1.record(rs)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        k_avg_s = ev0.elapsed_time(ev1) / 1e3 / args.steps
+        timed_kernels = ("the whole validate call, graph replay: k_plan, k_chain, k_resolve, k_walk, k_main, "
+                         "k_finalize, k_pass2, k_finalize")
     elapsed = t1 - t0
     value = W * args.steps / elapsed
     ms_per_step = 1e3 * elapsed / args.steps
-    k_avg_s = (k_ms / k_n) / 1e3
-    algo_bytes = 4.0 * W + 6.0 * n_inst
     achieved = algo_bytes / k_avg_s / 1e9
-    log(f"step {ms_per_step:.3f} ms, decode/validate kernels {1e3 * k_avg_s:.3f} ms, {achieved:.0f} GB/s algorithmic")
+    log(f"step {ms_per_step:.3f} ms, timed kernels {1e3 * k_avg_s:.3f} ms, {achieved:.0f} GB/s algorithmic")
 
     g = res.cpu().numpy().view(np.uint32)[0]
     checked = None
@@ -326,7 +359,7 @@ def main():
                    "parallelism": "1 GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_chain + k_resolve + k_walk (+ k_main, returns at once)",
+                     "kernel": timed_kernels,
                      "kernel_ms": 1e3 * k_avg_s,
                      "algorithmic_bytes": algo_bytes},
         "cpu_baseline": cpu,
