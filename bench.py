@@ -20,8 +20,9 @@ Also reported on the same JSON line:
                 committed rocprofv3 counter summary, when it was taken on
                 the current kernel code;
   cpu_baseline  the CPU oracle (single thread) on the same module;
-  batched       4096 lognormal modules with 41 injected faults per launch:
-                words/s and p50 / p99 per-launch latency.
+  batched       4096 lognormal modules with 41 injected faults per launch
+                (graph replays of one captured call): words/s and p50 / p99
+                per-launch latency.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -348,14 +349,23 @@ def main():
         for _ in range(3):
             spv.validate(w3, m3, ctx=ctx, out=(r3, i3, p3), workspace=ws3)
         torch.cuda.synchronize()
-        lat = []
+        # one launch = one replay of the captured call (as in the timed region)
+        g3, s3 = torch.cuda.CUDAGraph(), torch.cuda.Stream()
+        with torch.cuda.stream(s3):
+            with torch.cuda.graph(g3, stream=s3):
+                spv.validate(w3, m3, ctx=ctx, out=(r3, i3, p3), workspace=ws3, stream=s3)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            g3.replay()
+        torch.cuda.synchronize()
         n_rep = 50
+        rs = torch.cuda.current_stream()
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_rep)]
         tb0 = time.perf_counter()
         for a, b in ev:
-            a.record()
-            spv.validate(w3, m3, ctx=ctx, out=(r3, i3, p3), workspace=ws3)
-            b.record()
+            a.record(rs)
+            g3.replay()
+            b.record(rs)
         torch.cuda.synchronize()
         tb1 = time.perf_counter()
         lat = np.array([a.elapsed_time(b) for a, b in ev])
