@@ -105,6 +105,8 @@ int run_validate(spv_ctx* ctx, const uint32_t* words, const int64_t* mod_off, in
   p.semantic = semantic;
   p.index = index ? 1 : 0;
   p.sched_static = 0;
+  // small batches: the second pass decides its own work (no phase-1 launch)
+  p.p1_inline = (semantic && n_modules <= 256 && p.n_tiles > 0) ? 1 : 0;
   hipStream_t s = static_cast<hipStream_t>(stream);
 
   int64_t plan_units = n_modules > p.n_tiles ? n_modules : p.n_tiles;
@@ -165,8 +167,10 @@ int run_validate(spv_ctx* ctx, const uint32_t* words, const int64_t* mod_off, in
     }
   }
   if (semantic) {
-    spv::launch_finalize(p, 1, s);
-    if ((r = check_launch(ctx))) return r;
+    if (!p.p1_inline) {
+      spv::launch_finalize(p, 1, s);
+      if ((r = check_launch(ctx))) return r;
+    }
     int64_t g2 = int64_t(ctx->n_cu) * 2;
     if (g2 > p.n_tiles) g2 = p.n_tiles;
     if (g2 > 0) {

@@ -168,6 +168,7 @@ struct VParams {
   // cooperatively, so every block is resident); 0: tiles are claimed in
   // order from a counter
   int sched_static;
+  int p1_inline;  // k_pass2 computes finalize phase 1 itself (at most 256 modules; no k_finalize(1) launch)
 };
 
 // Grammar entry for opcode < 256 (index 256 = any other opcode):

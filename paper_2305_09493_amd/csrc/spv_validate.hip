@@ -2076,18 +2076,69 @@ __global__ __launch_bounds__(256) void k_finalize(VParams P, int phase) {
 // second pass: undefined-ID check for modules marked in phase 1.
 __global__ __launch_bounds__(kBlock) void k_pass2(VParams P) {
   __shared__ Shared S;
-  if (P.ctrl[kCtlPass2] == 0) return;
-  if (threadIdx.x == 0) S.cache_ok = 0;
-  init_table(S.tbl);
+  // small batches (p1_inline, at most kBlock modules): every block decides
+  // for itself which modules the pass needs and lists their tiles in LDS
+  // (the first finalize phase's work, no launch of it); the need flags are
+  // read from LDS, never from module state that other blocks write
+  __shared__ uint32_t s_need[kBlock / 32];
+  __shared__ uint32_t s_tpre[kBlock + 1];  // listed tiles before module m
   const int tid = threadIdx.x;
   const int wave = tid >> 6;
   const int lane = tid & 63;
+  long long n_list;
+  if (P.p1_inline) {
+    uint32_t nt = 0;
+    bool need = false;
+    if (tid < P.M) {
+      const ModState& ms = P.mods[tid];
+      if (ms.hdr_code == 0 && ms.err_key == ~0ull)
+        need = (ms.flags & kModSparse) || (ms.bound > 1u && ms.def_count < ms.bound - 1u);
+      const int64_t off = P.mod_off[tid], end = P.mod_off[tid + 1];
+      if (need && end > off) nt = uint32_t((end - 1) / kTileWords - off / kTileWords + 1);
+    }
+    const uint64_t nb = __ballot(need);
+    if (lane == 0) {
+      s_need[2 * wave] = uint32_t(nb);
+      s_need[2 * wave + 1] = uint32_t(nb >> 32);
+    }
+    const uint32_t inc = wave_incl_sum(nt);
+    if (lane == 63) S.wcnt[wave] = inc;
+    __syncthreads();
+    uint32_t pre = 0, tot = 0;
+    for (int w = 0; w < kWaves; ++w) {
+      if (w < wave) pre += S.wcnt[w];
+      tot += S.wcnt[w];
+    }
+    s_tpre[tid] = pre + inc - nt;
+    if (tid == 0) s_tpre[kBlock] = tot;
+    __syncthreads();
+    n_list = tot;
+    if (n_list == 0) return;  // the same in every block
+  } else {
+    if (P.ctrl[kCtlPass2] == 0) return;
+    n_list = P.ctrl[kCtlP2Tiles];
+  }
+  auto marked = [&](int64_t m) -> bool {
+    return P.p1_inline ? ((s_need[m >> 5] >> (m & 31)) & 1u) != 0 : (P.mods[m].flags & kModPass2) != 0;
+  };
+  if (threadIdx.x == 0) S.cache_ok = 0;
+  init_table(S.tbl);
   // tiles of the marked modules, listed by the first finalize phase, in
   // block order (a tile of two marked modules may come twice: the checks
   // only set flags)
-  const long long n_list = P.ctrl[kCtlP2Tiles];
   for (long long li = blockIdx.x; li < n_list; li += gridDim.x) {
-    const long long t = P.p2list[li];
+    long long t;
+    if (P.p1_inline) {
+      int lo = 0, hi = int(P.M) - 1;  // last module with s_tpre[m] <= li
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_tpre[mid] <= uint32_t(li)) lo = mid;
+        else hi = mid - 1;
+      }
+      t = P.mod_off[lo] / kTileWords + (li - s_tpre[lo]);
+    } else {
+      t = P.p2list[li];
+    }
     const int64_t t0 = t * kTileWords;
     const int64_t t1 = (t0 + kTileWords < P.W) ? t0 + kTileWords : P.W;
     if (wave == 0) build_list(S, P, t, t0, t1);
@@ -2095,7 +2146,7 @@ __global__ __launch_bounds__(kBlock) void k_pass2(VParams P) {
     // any module of this tile marked?
     bool mark = false;
     for (int j = 0; j < (S.crowded ? 0 : S.K); ++j)
-      if (S.list[j].mod >= 0 && (P.mods[S.list[j].mod].flags & kModPass2)) mark = true;
+      if (S.list[j].mod >= 0 && marked(S.list[j].mod)) mark = true;
     if (S.crowded) mark = true;
     if (!mark) {
       __syncthreads();
@@ -2108,7 +2159,7 @@ __global__ __launch_bounds__(kBlock) void k_pass2(VParams P) {
         int64_t m = P.tfm[t];
         for (; m < P.M && P.mod_off[m] < t1; ++m) {
           ModState& ms = P.mods[m];
-          if (!(ms.flags & kModPass2)) continue;
+          if (!marked(m)) continue;
           int64_t off = P.mod_off[m], end = P.mod_off[m + 1];
           if (ms.flags & kModSparse) {
             int64_t s0 = off > t0 ? off : t0, s1 = end < t1 ? end : t1;
@@ -2126,7 +2177,7 @@ __global__ __launch_bounds__(kBlock) void k_pass2(VParams P) {
         const LEnt& le = S.list[j];
         if (le.mod < 0 || !(le.info & kInfoSparse)) continue;
         ModState& ms = P.mods[le.mod];
-        if (!(ms.flags & kModPass2)) continue;
+        if (!marked(le.mod)) continue;
         int64_t s0 = le.off > t0 ? le.off : t0, s1 = le.end < t1 ? le.end : t1;
         bool bad = false;
         for (int64_t i = s0 + tid; i < s1; i += kBlock) {
@@ -2204,7 +2255,7 @@ __global__ __launch_bounds__(kBlock) void k_pass2(VParams P) {
             const LEnt& le = S.list[jm];
             if (le.mod < 0 || (le.info & kInfoSparse) || !(le.info & kInfoHdrOk)) return;
             ModState& ms = P.mods[le.mod];
-            if (!(ms.flags & kModPass2)) return;
+            if (!marked(le.mod)) return;
             if (v == 0u || v >= le.bound) return;
             unsigned long long word = P.idmap[le.off + (v >> 6)];
             if (!((word >> (v & 63u)) & 1ull)) atomicOr(&ms.flags, kModUndef);
@@ -2235,7 +2286,7 @@ __global__ __launch_bounds__(kBlock) void k_pass2(VParams P) {
       }
       for (;;) {
         ModState& ms = P.mods[m];
-        bool act = (ms.flags & kModPass2) && !(ms.flags & kModSparse);
+        bool act = marked(m) && !(ms.flags & kModSparse);
         while (pos >= 0 && pos < end && pos < t1) {
           if (start_code(P.words, S.tbl, pos, end)) {
             pos = -1;
