@@ -22,6 +22,7 @@ _lock = threading.Lock()
 OK, E_TRUNCATED_HEADER, E_BAD_MAGIC, E_BAD_VERSION, E_BAD_SCHEMA = 0, 1, 2, 3, 4
 E_BAD_WORD_COUNT, E_UNKNOWN_OPCODE, E_BAD_STRING = 5, 6, 7
 E_ID_OUT_OF_BOUND, E_DUPLICATE_ID, E_UNDEFINED_ID = 8, 9, 10
+E_MODULE_RULES = 11  # with rules: sem_mask = 8 no OpCapability | 16 no OpMemoryModel | 32 no OpFunction
 ENC_OK, ENC_UNKNOWN_OPCODE, ENC_OPERAND_COUNT, ENC_BAD_STRING, ENC_TOO_LONG, ENC_BAD_ID = range(6)
 
 RESULT_DTYPE = np.dtype([("code", "<u4"), ("sem_mask", "<u4"), ("err_word", "<u4"), ("n_inst", "<u4")])
@@ -43,7 +44,7 @@ def _load():
             build()
             lib = ctypes.CDLL(_LIB_PATH)
             P = ctypes.c_void_p
-            lib.oracle_validate.argtypes = [P, P, ctypes.c_int64, ctypes.c_int, P, P, P]
+            lib.oracle_validate.argtypes = [P, P, ctypes.c_int64, ctypes.c_int, ctypes.c_int, P, P, P]
             lib.oracle_validate.restype = ctypes.c_int
             lib.oracle_records.argtypes = [P, P, ctypes.c_int64, P, P, P, P, P, P]
             lib.oracle_records.restype = ctypes.c_int
@@ -64,10 +65,12 @@ def _contig(a, dtype):
     return np.ascontiguousarray(np.asarray(a, dtype=dtype))
 
 
-def validate(words, mod_off, semantic: bool = True, index: bool = True):
+def validate(words, mod_off, semantic: bool = True, index: bool = True, rules: bool = False):
     """Per-module results (structured array) and, if index, the gapped-CSR
     instruction index (idx_off uint32[W], idx_op uint16[W]; entries past each
-    module's n_inst are left 0)."""
+    module's n_inst are left 0).  With semantic and rules, modules that pass
+    every check are held to the module-level rules (section "Validation
+    Rules"; code E_MODULE_RULES)."""
     lib = _load()
     words = _contig(words, np.uint32)
     mod_off = _contig(mod_off, np.int64)
@@ -75,7 +78,7 @@ def validate(words, mod_off, semantic: bool = True, index: bool = True):
     res = np.zeros(m, dtype=RESULT_DTYPE)
     idx_off = np.zeros(words.size, np.uint32) if index else None
     idx_op = np.zeros(words.size, np.uint16) if index else None
-    rc = lib.oracle_validate(_ptr(words), _ptr(mod_off), m, int(bool(semantic)),
+    rc = lib.oracle_validate(_ptr(words), _ptr(mod_off), m, int(bool(semantic)), int(bool(rules)),
                              _ptr(idx_off) if index else None, _ptr(idx_op) if index else None, _ptr(res))
     if rc != 0:
         raise RuntimeError("oracle_validate failed")

@@ -47,6 +47,7 @@ enum {
   ORC_ID_OUT_OF_BOUND = 8,
   ORC_DUPLICATE_ID = 9,
   ORC_UNDEFINED_ID = 10,
+  ORC_MODULE_RULES = 11,
 };
 enum {
   ORC_ENC_OK = 0,
@@ -127,10 +128,31 @@ static int contains(const uint32_t *sorted, uint64_t n, uint32_t v) {
   return lo < n && sorted[lo] == v;
 }
 
+/* Module-level rules (section "Validation Rules"), a stage after the
+ * semantic one for a module that passed it: the module must declare a
+ * capability (OpCapability, 17), define its memory model (OpMemoryModel, 14)
+ * and declare a function (OpFunction, 54).  The fourth rule of that section,
+ * an entry point, needs OpEntryPoint (15), which is outside the twelve-opcode
+ * grammar: a module holding one has already failed the parse stage, so the
+ * rule is not checked here.  Returns the missing rules as 8 (capability) |
+ * 16 (memory model) | 32 (function). */
+static uint32_t missing_rules(const uint32_t *w, uint64_t n) {
+  int capability = 0, memory_model = 0, function = 0;
+  for (uint64_t p = 5; p < n; p += w[p] >> 16) {
+    uint32_t op = w[p] & 0xFFFFu;
+    if (op == 17) capability = 1;
+    if (op == 14) memory_model = 1;
+    if (op == 54) function = 1;
+  }
+  return (capability ? 0u : 8u) | (memory_model ? 0u : 16u) | (function ? 0u : 32u);
+}
+
 /* Decode (and, if semantic != 0, validate) one module w[0..n).  Instruction
  * j of the valid prefix goes to idx_off[j] / idx_op[j] when they are given.
+ * With semantic and rules, a module that passes every check is then held to
+ * the module-level rules.
  * Returns 0, or -1 if memory for the semantic stage could not be had. */
-static int check_module(const uint32_t *w, uint64_t n, int semantic, uint32_t *idx_off, uint16_t *idx_op,
+static int check_module(const uint32_t *w, uint64_t n, int semantic, int rules, uint32_t *idx_off, uint16_t *idx_op,
                         orc_result *r) {
   r->code = ORC_OK;
   r->sem_mask = 0;
@@ -227,6 +249,10 @@ static int check_module(const uint32_t *w, uint64_t n, int semantic, uint32_t *i
   if (oob) r->code = ORC_ID_OUT_OF_BOUND;
   else if (dup) r->code = ORC_DUPLICATE_ID;
   else if (undef) r->code = ORC_UNDEFINED_ID;
+  if (rules && r->code == ORC_OK) {
+    r->sem_mask = missing_rules(w, n);
+    if (r->sem_mask) r->code = ORC_MODULE_RULES;
+  }
   return 0;
 }
 
@@ -234,12 +260,12 @@ static int check_module(const uint32_t *w, uint64_t n, int semantic, uint32_t *i
  * words[mod_off[m] .. mod_off[m+1]).  Index arrays, when given, are gapped
  * CSR: module m's instruction j is at idx_off[mod_off[m] + j] (a word offset
  * within the module) and idx_op[mod_off[m] + j].  Returns 0 or -1. */
-int oracle_validate(const uint32_t *words, const int64_t *mod_off, int64_t n_modules, int semantic,
+int oracle_validate(const uint32_t *words, const int64_t *mod_off, int64_t n_modules, int semantic, int rules,
                     uint32_t *idx_off, uint16_t *idx_op, orc_result *results) {
   for (int64_t m = 0; m < n_modules; ++m) {
     int64_t b = mod_off[m], e = mod_off[m + 1];
     if (e < b) return -1;
-    if (check_module(words + b, (uint64_t)(e - b), semantic, idx_off ? idx_off + b : NULL,
+    if (check_module(words + b, (uint64_t)(e - b), semantic, rules, idx_off ? idx_off + b : NULL,
                      idx_op ? idx_op + b : NULL, &results[m]) != 0)
       return -1;
   }
@@ -263,7 +289,7 @@ int oracle_records(const uint32_t *words, const int64_t *mod_off, int64_t n_modu
     const uint32_t *w = words + b;
     uint64_t n = (uint64_t)(e - b);
     orc_result r;
-    check_module(w, n, 0, NULL, NULL, &r);
+    check_module(w, n, 0, 0, NULL, NULL, &r);
     if (r.code == ORC_OK || r.code >= ORC_BAD_WORD_COUNT) {
       uint64_t p = 5;
       for (uint32_t j = 0; j < r.n_inst; ++j) {

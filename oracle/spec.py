@@ -42,7 +42,12 @@ def _string_words_ok(raw: bytes) -> bool:
     return nul >= len(raw) - 4 and raw[nul:] == b"\x00" * (len(raw) - nul)
 
 
-def check(words, semantic: bool = True):
+# module-level rules (section "Validation Rules") checkable with the twelve
+# opcodes: mask bit of each rule -> the opcodes that satisfy it
+RULES = {8: {17}, 16: {14}, 32: {54}}   # a capability, the memory model, a function
+
+
+def check(words, semantic: bool = True, rules: bool = False):
     """(code, sem_mask, err_word, n_inst, [(offset, opcode), ...])."""
     w = [int(x) & 0xFFFFFFFF for x in words]
     n = len(w)
@@ -96,6 +101,10 @@ def check(words, semantic: bool = True):
     undef = bool(used - set(defined))
     mask = (1 if out_of_bound else 0) | (2 if dup else 0) | (4 if undef else 0)
     code = 8 if out_of_bound else 9 if dup else 10 if undef else 0
+    if rules and code == 0:
+        present = Counter(opcode for _, opcode in insts)
+        mask = sum(bit for bit, ops in RULES.items() if not any(present[o] for o in ops))
+        code = 11 if mask else 0
     return (code, mask, 0xFFFFFFFF, len(insts), insts)
 
 

@@ -76,17 +76,18 @@ def _mutations(base, rng):
     return out
 
 
-def _compare(mods, semantic):
+def _compare(mods, semantic, rules=False):
     sizes = np.array([len(m) for m in mods], np.int64)
     mod_off = np.concatenate([[0], np.cumsum(sizes)])
     words = np.array([x for m in mods for x in m], np.uint32)
-    res, io, iop = oracle.validate(words, mod_off, semantic=semantic)
+    res, io, iop = oracle.validate(words, mod_off, semantic=semantic, rules=rules)
     for i, m in enumerate(mods):
-        code, mask, err, n_inst, insts = spec.check(m, semantic=semantic)
+        code, mask, err, n_inst, insts = spec.check(m, semantic=semantic, rules=rules)
         got = tuple(int(res[i][k]) for k in ("code", "sem_mask", "err_word", "n_inst"))
         assert got == (code, mask, err, n_inst), (m, got)
         b = mod_off[i]
         assert [(int(io[b + j]), int(iop[b + j])) for j in range(n_inst)] == insts
+    return res
 
 
 def test_bruteforce_small_modules():
@@ -138,3 +139,18 @@ def test_bruteforce_encode():
             assert (int(code[i]), int(bad[i])) == exp and wmo[i + 1] == wmo[i], (recs, code[i], bad[i])
         else:
             assert code[i] == 0 and [int(x) for x in w[wmo[i]:wmo[i + 1]]] == exp, recs
+
+
+def test_bruteforce_module_rules():
+    """With the module-level rules: every presence pattern of the three rule
+    opcodes occurs among sequences of up to three instructions."""
+    mods = _modules()
+    res = _compare(mods, True, rules=True)
+    rules = res["code"] == oracle.E_MODULE_RULES
+    assert set(int(x) for x in np.unique(res["sem_mask"][rules])) == {8, 16, 24, 32, 40, 48, 56}
+    assert int(np.sum(res["code"] == 0)) > 0
+    # without the rules the same modules keep their codes, except that rule
+    # failures read as valid
+    plain = _compare(mods, True)
+    assert np.array_equal(plain["code"][~rules], res["code"][~rules])
+    assert np.all(plain["code"][rules] == 0)
