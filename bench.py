@@ -171,6 +171,35 @@ def records_leg(ctx, words, mod_off, idx_off, res, W, steps=10):
             "hbm_frac": bytes_moved / dt / 1e9 / HBM_PEAK_GBS}
 
 
+def rules_leg(ctx, words, mod_off, plain_ms, steps=10):
+    """The validate call with the module-level rules (a capability, the
+    memory model, a function) as a last stage, on the timed module: graph
+    replays of the captured call, and the time the rules add to the plain
+    call's step."""
+    import torch
+
+    import paper_2305_09493_amd as spv
+    out = spv.validate(words, mod_off, ctx=ctx, module_rules=True)
+    torch.cuda.synchronize()
+    graph, gs = torch.cuda.CUDAGraph(), torch.cuda.Stream()
+    with torch.cuda.stream(gs):
+        with torch.cuda.graph(graph, stream=gs):
+            out = spv.validate(words, mod_off, ctx=ctx, stream=gs, module_rules=True)
+    torch.cuda.synchronize()
+    graph.replay()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(steps):
+        graph.replay()
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    res = out[0].cpu().numpy()
+    return {"ms_per_call": ms, "extra_ms_over_plain_step": ms - plain_ms,
+            "module_code": int(res[0, 0]), "module_sem_mask": int(res[0, 1])}
+
+
 def serve_leg(args):
     """Poisson stream of validate requests: continuous batching vs one module
     per launch, same streams, kernels and arrival trace."""
@@ -210,6 +239,8 @@ def main():
     ap.add_argument("--cache", default=None, help="npy file to keep the generated module between runs")
     ap.add_argument("--encode", action="store_true", help="add the encode leg (10M records, 1024 modules)")
     ap.add_argument("--records", action="store_true", help="add the records-mode leg (records of the timed module)")
+    ap.add_argument("--module-rules", action="store_true",
+                    help="add the leg of the validate call with the module-level rules")
     ap.add_argument("--serve", action="store_true", help="add the serving leg (Poisson stream, batched vs "
                                                          "one module per launch)")
     ap.add_argument("--serve-rates", default="20000", help="comma-separated arrival rates for --serve")
@@ -375,6 +406,7 @@ def main():
                    "modules_flagged": faults, "launches": n_rep}
 
     records = records_leg(ctx, words, mod_off, idx_off, res, W) if args.records else None
+    rules = rules_leg(ctx, words, mod_off, ms_per_step) if args.module_rules else None
     encode = encode_leg(ctx, dev) if args.encode else None
     serving = serve_leg(args) if args.serve else None
 
@@ -407,6 +439,8 @@ def main():
     }
     if records is not None:
         line["records"] = records
+    if rules is not None:
+        line["module_rules"] = rules
     if encode is not None:
         line["encode"] = encode
     if serving is not None:

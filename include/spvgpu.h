@@ -73,6 +73,16 @@ extern "C" {
 #define SPV_E_ID_OUT_OF_BOUND 8
 #define SPV_E_DUPLICATE_ID 9
 #define SPV_E_UNDEFINED_ID 10
+/* (spv_validate with SPV_OPT_MODULE_RULES) a module that passed every check
+ * above lacks what section "Validation Rules" requires of every module:
+ * sem_mask = 8 no OpCapability | 16 no OpMemoryModel | 32 no OpFunction.
+ * The section's entry-point rule is not checked: OpEntryPoint is outside the
+ * grammar table, so a module holding one fails with UNKNOWN_OPCODE first. */
+#define SPV_E_MODULE_RULES 11
+
+/* spv_validate option: hold modules that pass every check to the
+ * module-level rules (SPV_E_MODULE_RULES).  Needs the instruction index. */
+#define SPV_OPT_MODULE_RULES 1u
 
 /* ---- encode status codes (per module) ---------------------------------- */
 #define SPV_ENC_OK 0
@@ -102,7 +112,7 @@ typedef struct spv_ctx spv_ctx;
 /* 16 bytes per module. */
 typedef struct {
   uint32_t code;     /* SPV_OK or SPV_E_* */
-  uint32_t sem_mask; /* 1 OOB | 2 DUP | 4 UNDEF (validate; 0 otherwise) */
+  uint32_t sem_mask; /* 1 OOB | 2 DUP | 4 UNDEF (validate); missing rules (SPV_E_MODULE_RULES); else 0 */
   uint32_t err_word; /* offending word offset within the module, or 0xFFFFFFFF */
   uint32_t n_inst;   /* instructions decoded (before the failing one, if any) */
 } spv_result;
@@ -147,8 +157,10 @@ int spv_decode(spv_ctx *ctx, const uint32_t *words, const int64_t *mod_off, int6
                size_t ws_bytes, void *stream);
 
 /* Validate: decode plus the semantic stage (bound, define-once, undefined
- * IDs).  Same arguments as spv_decode, plus option_flags (must be 0; reserved
- * for the paper's module-level rules). */
+ * IDs).  Same arguments as spv_decode, plus option_flags: 0, or
+ * SPV_OPT_MODULE_RULES to add the module-level rules of section "Validation
+ * Rules" as a last stage (SPV_ERR_INVALID_ARG for other bits, or for the
+ * rules without idx_op when n_words > 0). */
 int spv_validate(spv_ctx *ctx, const uint32_t *words, const int64_t *mod_off, int64_t n_modules, int64_t n_words,
                  uint32_t *idx_off, uint16_t *idx_op, int64_t idx_cap, spv_result *results, uint32_t option_flags,
                  void *ws, size_t ws_bytes, void *stream);

@@ -26,6 +26,8 @@ ERRORS = {-1: "invalid argument", -2: "capacity", -3: "workspace", -4: "HIP erro
 OK, E_TRUNCATED_HEADER, E_BAD_MAGIC, E_BAD_VERSION, E_BAD_SCHEMA = 0, 1, 2, 3, 4
 E_BAD_WORD_COUNT, E_UNKNOWN_OPCODE, E_BAD_STRING = 5, 6, 7
 E_ID_OUT_OF_BOUND, E_DUPLICATE_ID, E_UNDEFINED_ID = 8, 9, 10
+E_MODULE_RULES = 11  # validate(module_rules=True): sem_mask = 8 no capability | 16 no memory model | 32 no function
+OPT_MODULE_RULES = 1
 E_SPIN_LIMIT = 0xDEAD  # every result of a call whose inter-block wait gave up (repeat the call)
 ENC_OK, ENC_UNKNOWN_OPCODE, ENC_OPERAND_COUNT, ENC_BAD_STRING, ENC_TOO_LONG, ENC_BAD_ID, ENC_CAPACITY = range(7)
 
@@ -173,7 +175,8 @@ def _stream(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-def _run(semantic: bool, words, mod_off, index: bool, ctx: Optional[Context], stream, out=None, workspace=None):
+def _run(semantic: bool, words, mod_off, index: bool, ctx: Optional[Context], stream, out=None, workspace=None,
+         flags: int = 0):
     torch = _torch()
     ctx = ctx or context(words.device.index)
     W = int(words.numel())
@@ -192,7 +195,7 @@ def _run(semantic: bool, words, mod_off, index: bool, ctx: Optional[Context], st
     args = [ctx.h, _ptr(words), _ptr(mod_off), M, W, _ptr(idx_off), _ptr(idx_op), W if index else 0,
             _ptr(results)]
     if semantic:
-        rc = ctx.lib.spv_validate(*args, 0, _ptr(ws), ws.numel(), _stream(stream))
+        rc = ctx.lib.spv_validate(*args, flags, _ptr(ws), ws.numel(), _stream(stream))
         ctx.check(rc, "spv_validate")
     else:
         rc = ctx.lib.spv_decode(*args, _ptr(ws), ws.numel(), _stream(stream))
@@ -201,11 +204,15 @@ def _run(semantic: bool, words, mod_off, index: bool, ctx: Optional[Context], st
 
 
 def validate(words, mod_off, index: bool = True, ctx: Optional[Context] = None, stream=None, out=None,
-             workspace=None):
+             workspace=None, module_rules: bool = False):
     """Per-module results int32[M, 4] (code, sem_mask, err_word, n_inst) and,
     if index, the gapped-CSR instruction index (idx_off int32[W], idx_op
-    int16[W])."""
-    return _run(True, words, mod_off, index, ctx, stream, out, workspace)
+    int16[W]).  module_rules adds the module-level rules as a last stage
+    (E_MODULE_RULES; needs the index)."""
+    if module_rules and not index:
+        raise SpvError("module_rules needs the instruction index (index=True)")
+    return _run(True, words, mod_off, index, ctx, stream, out, workspace,
+                OPT_MODULE_RULES if module_rules else 0)
 
 
 def decode(words, mod_off, index: bool = True, ctx: Optional[Context] = None, stream=None, out=None,

@@ -287,9 +287,16 @@ int spv_decode(spv_ctx* ctx, const uint32_t* words, const int64_t* mod_off, int6
 int spv_validate(spv_ctx* ctx, const uint32_t* words, const int64_t* mod_off, int64_t n_modules, int64_t n_words,
                  uint32_t* idx_off, uint16_t* idx_op, int64_t idx_cap, spv_result* results, uint32_t option_flags,
                  void* ws, size_t ws_bytes, void* stream) {
-  if (option_flags != 0) return SPV_ERR_INVALID_ARG;
-  return run_validate(ctx, words, mod_off, n_modules, n_words, idx_off, idx_op, idx_cap, results, 1, ws, ws_bytes,
-                      stream);
+  if ((option_flags & ~SPV_OPT_MODULE_RULES) != 0) return SPV_ERR_INVALID_ARG;
+  const bool rules = (option_flags & SPV_OPT_MODULE_RULES) != 0;
+  if (rules && n_words > 0 && !idx_op) return SPV_ERR_INVALID_ARG;
+  const int rc = run_validate(ctx, words, mod_off, n_modules, n_words, idx_off, idx_op, idx_cap, results, 1, ws,
+                              ws_bytes, stream);
+  if (rc != SPV_SUCCESS || !rules || n_modules == 0) return rc;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail_hip(ctx, hipErrorInvalidDevice);
+  spv::launch_rules(idx_op, mod_off, results, n_modules, n_words, static_cast<hipStream_t>(stream));
+  return check_launch(ctx);
 }
 
 int spv_encode_bound(int64_t n_modules, int64_t n_records, int64_t n_opnd_words, int64_t n_string_records,

@@ -297,5 +297,8 @@ inline RLayout make_rlayout(int64_t n_modules, int64_t n_words) {
 }
 
 void launch_records(const RParams& p, hipStream_t s);
+// module-level rules over the index of a finished validate call
+void launch_rules(const uint16_t* idx_op, const int64_t* mod_off, spv_result* results, int64_t M, int64_t W,
+                  hipStream_t s);
 
 }  // namespace spv

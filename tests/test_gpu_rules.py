@@ -1,0 +1,117 @@
+"""GPU parity of the module-level rules (spv_validate with
+SPV_OPT_MODULE_RULES) against the oracle's rules stage: mixed batches with
+modules lacking each rule (rewritten so that every ID check still passes),
+modules failing earlier stages, header-only, short and empty modules, a
+multi-tile module without functions, and the full lognormal batch."""
+import numpy as np
+import pytest
+
+import oracle
+import spvgen
+from spvgen import K_CAP, K_FUNC, K_MEM, K_TYPEINT
+
+pytestmark = pytest.mark.gpu
+
+
+def _type_id(mod):
+    """Result ID of the module's first OpTypeInt (defined in every generated module)."""
+    s = int(mod.starts[np.nonzero(mod.kind == K_TYPEINT)[0][0]])
+    return int(mod.words[s + 1])
+
+
+def drop_capability(mod):
+    """Every OpCapability becomes an OpLabel defining a fresh ID (bound raised)."""
+    w = mod.words.copy()
+    bound = int(w[3])
+    for s in mod.starts[mod.kind == K_CAP]:
+        w[s] = (2 << 16) | 248
+        w[s + 1] = bound
+        bound += 1
+    w[3] = bound
+    return w
+
+
+def drop_memory_model(mod):
+    """Every OpMemoryModel becomes OpStore %t %t (t: the module's int type)."""
+    w = mod.words.copy()
+    t = _type_id(mod)
+    for s in mod.starts[mod.kind == K_MEM]:
+        w[s] = (3 << 16) | 62
+        w[s + 1] = t
+        w[s + 2] = t
+    return w
+
+
+def drop_functions(mod):
+    """Every OpFunction becomes an OpIAdd with the same result (its control
+    literal becomes a use of the int type)."""
+    w = mod.words.copy()
+    t = _type_id(mod)
+    for s in mod.starts[mod.kind == K_FUNC]:
+        w[s] = (5 << 16) | 128
+        w[s + 3] = t
+    return w
+
+
+def _run(words_list, label):
+    import torch
+
+    import paper_2305_09493_amd as spv
+    from gpu_util import to_dev
+    sizes = np.array([w.size for w in words_list], np.int64)
+    mod_off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    words = np.concatenate(words_list).astype(np.uint32) if words_list else np.zeros(0, np.uint32)
+    print(f"[rules parity] {label}: M={len(words_list)} W={words.size}", flush=True)
+    w, mo = to_dev(words, mod_off)
+    res, io, iop = spv.validate(w, mo, module_rules=True)
+    torch.cuda.synchronize()
+    g = res.cpu().numpy().view(np.uint32)
+    o, oio, oiop = oracle.validate(words, mod_off, semantic=True, rules=True)
+    o_arr = np.stack([o[k] for k in ("code", "sem_mask", "err_word", "n_inst")], axis=1).astype(np.uint32)
+    bad = np.nonzero(np.any(g != o_arr, axis=1))[0]
+    assert bad.size == 0, [(int(m), g[m].tolist(), o_arr[m].tolist()) for m in bad[:8]]
+    # the index is the plain validate call's
+    gio = io.cpu().numpy().view(np.uint32)
+    giop = iop.cpu().numpy().view(np.uint16)
+    for m in range(len(words_list)):
+        b, n = int(mod_off[m]), int(o_arr[m, 3])
+        assert np.array_equal(gio[b:b + n], oio[b:b + n]) and np.array_equal(giop[b:b + n], oiop[b:b + n]), m
+    return o_arr
+
+
+def test_rules_mixed_batch():
+    mods = [spvgen.gen_module([11, i], n) for i, n in enumerate([3, 4, 9, 40, 200, 3000, 60_000, 20_000, 700])]
+    words = [m.words for m in mods]
+    words += [drop_capability(mods[5]), drop_memory_model(mods[4]), drop_functions(mods[6]),
+              drop_functions(mods[7]), drop_capability(mods[3])]
+    both = spvgen.gen_module([11, 99], 5000)
+    w = drop_memory_model(both)
+    both.words = w
+    words.append(drop_capability(both))
+    words.append(drop_functions(both))
+    # earlier stages win: a duplicate ID in a module without functions
+    dup = spvgen.inject_dup(spvgen.gen_module([11, 77], 900), np.random.default_rng(5))
+    dup.words = drop_functions(dup)
+    words.append(dup.words)
+    words += [np.array([0x07230203, 0x00010600, 0, 1, 0], np.uint32), np.zeros(0, np.uint32),
+              np.array([0x07230203, 0x00010600, 0], np.uint32)]
+    o = _run(words, "mixed")
+    codes = set(int(c) for c in o[:, 0])
+    masks = set(int(s) for c, s in zip(o[:, 0], o[:, 1]) if c == oracle.E_MODULE_RULES)
+    assert {0, 1, 9, oracle.E_MODULE_RULES} <= codes
+    assert {8, 16, 32, 56} <= masks
+
+
+def test_rules_single_module_without_functions():
+    mod = spvgen.gen_module([12, 1], 400_000)
+    o = _run([drop_functions(mod)], "one module, 400k instructions, no OpFunction")
+    assert (int(o[0, 0]), int(o[0, 1])) == (oracle.E_MODULE_RULES, 32)
+    o = _run([mod.words], "the same module as generated")
+    assert int(o[0, 0]) == 0
+
+
+def test_rules_full_batched_workload():
+    b = spvgen.config3()
+    words = [b.words[b.mod_off[m]:b.mod_off[m + 1]] for m in range(b.n_modules)]
+    o = _run(words, "lognormal batch, full size")
+    assert int(np.sum(o[:, 0] == 0)) > 3000
