@@ -2,7 +2,8 @@
 SPV_OPT_MODULE_RULES) against the oracle's rules stage: mixed batches with
 modules lacking each rule (rewritten so that every ID check still passes),
 modules failing earlier stages, header-only, short and empty modules, a
-multi-tile module without functions, and the full lognormal batch."""
+multi-tile module without functions, the full lognormal batch, and graph
+replays of the captured call on changing inputs."""
 import numpy as np
 import pytest
 
@@ -115,3 +116,56 @@ def test_rules_full_batched_workload():
     words = [b.words[b.mod_off[m]:b.mod_off[m + 1]] for m in range(b.n_modules)]
     o = _run(words, "lognormal batch, full size")
     assert int(np.sum(o[:, 0] == 0)) > 3000
+
+
+def test_rules_graph_replays():
+    """The validate call with the rules, captured once and replayed on new
+    inputs of the same shape (modules with and without each rule swapped in
+    place), eager work between replays; every replay against the oracle."""
+    import torch
+
+    import paper_2305_09493_amd as spv
+    base = [spvgen.gen_module([13, i], 2000) for i in range(12)]
+    variants = [lambda m: m.words, drop_capability, drop_memory_model, drop_functions]
+
+    def batch(seed):
+        return [variants[(i + seed) % 4](m) for i, m in enumerate(base)]
+
+    w0 = batch(0)
+    sizes = np.array([w.size for w in w0], np.int64)
+    mod_off_h = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    W, M = int(mod_off_h[-1]), len(w0)
+    words = torch.zeros(W, dtype=torch.int32, device="cuda")
+    mod_off = torch.from_numpy(mod_off_h).cuda()
+    res = torch.empty((M, 4), dtype=torch.int32, device="cuda")
+    io = torch.empty(W, dtype=torch.int32, device="cuda")
+    iop = torch.empty(W, dtype=torch.int16, device="cuda")
+    ctx = spv.context()
+    ws = torch.empty(ctx.workspace_size(M, W), dtype=torch.uint8, device="cuda")
+    words.copy_(torch.from_numpy(np.concatenate(w0).view(np.int32)))
+    spv.validate(words, mod_off, out=(res, io, iop), workspace=ws, module_rules=True)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            spv.validate(words, mod_off, out=(res, io, iop), workspace=ws, stream=s, module_rules=True)
+    torch.cuda.synchronize()
+    seen = set()
+    for seed in [1, 2, 3, 0, 1]:
+        wl = batch(seed)
+        assert [w.size for w in wl] == sizes.tolist()
+        host = np.concatenate(wl).astype(np.uint32)
+        words.copy_(torch.from_numpy(host.view(np.int32)))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        got = res.cpu().numpy().view(np.uint32)
+        o = oracle.validate(host, mod_off_h, semantic=True, index=False, rules=True)
+        want = np.stack([o[k] for k in ("code", "sem_mask", "err_word", "n_inst")], axis=1).astype(np.uint32)
+        assert np.array_equal(got, want), (seed, got[:, :2].tolist(), want[:, :2].tolist())
+        seen |= set(int(x) for x in want[:, 1])
+        # eager work between replays
+        spv.validate(words, mod_off, out=(res, io, iop), workspace=ws)
+        torch.cuda.synchronize()
+    assert {8, 16} <= seen
