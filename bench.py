@@ -23,6 +23,10 @@ Also reported on the same JSON line:
   batched       4096 lognormal modules with 41 injected faults per launch
                 (graph replays of one captured call): words/s and p50 / p99
                 per-launch latency.
+Optional legs: --encode (10M records in 1024 modules), --records (decode's
+records mode on the timed module), --module-rules (the validate call with
+the module-level rules), --serve (Poisson stream, batched vs one module per
+launch).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
