@@ -31,7 +31,7 @@ RESULT_DTYPE = np.dtype([("code", "<u4"), ("sem_mask", "<u4"), ("err_word", "<u4
 def build(force: bool = False) -> str:
     """Compile oracle.c into liboracle.so with gcc (plain -O2, no SIMD flags)."""
     if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
-        tmp = _LIB_PATH + ".tmp"
+        tmp = f"{_LIB_PATH}.tmp{os.getpid()}"  # parallel test workers may build at once
         subprocess.check_call(["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-shared", "-fPIC", "-o", tmp, _SRC])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH

@@ -20,7 +20,8 @@
  *     (section "Validation Rules").
  * SPIR-V binary facts used: magic 0x07230203, schema word 0, first word of an
  * instruction = (word count << 16) | opcode.  The grammar table below is this
- * file's own copy of the twelve opcodes of the synthetic workload.
+ * file's own copy of the twelve opcodes of the synthetic workload plus
+ * OpEntryPoint, which the module-level rules need.
  *
  * Where the paper is silent the readings are: word counts are in words and
  * include the first word; the undefined-ID rule means "defined anywhere in the
@@ -62,9 +63,12 @@ typedef struct {
   uint32_t code, sem_mask, err_word, n_inst;
 } orc_result;
 
-/* One grammar entry: opcode, word count (0 = OpName: >= 3, operand then a
- * string), and the role of each operand word after the first word:
- * 'U' ID use, 'D' result ID, 'L' literal, 'S' string words to the end. */
+/* One grammar entry: opcode, word count (0 = variable: the operands before
+ * the 'S' role, then a string that runs to the last word), and the role of
+ * each operand word after the first word: 'U' ID use, 'D' result ID,
+ * 'L' literal, 'S' string words to the end.  OpEntryPoint's interface IDs,
+ * which in SPIR-V may follow its name, are not part of this grammar: its
+ * string must end in its last word. */
 typedef struct {
   uint16_t opcode;
   uint16_t word_count;
@@ -74,6 +78,7 @@ typedef struct {
 static const orc_inst GRAMMAR[] = {
     {5, 0, "US"},     /* OpName         */
     {14, 3, "LL"},    /* OpMemoryModel  */
+    {15, 0, "LUS"},   /* OpEntryPoint   */
     {17, 2, "L"},     /* OpCapability   */
     {21, 4, "DLL"},   /* OpTypeInt      */
     {43, 4, "UDL"},   /* OpConstant     */
@@ -85,12 +90,19 @@ static const orc_inst GRAMMAR[] = {
     {248, 2, "D"},    /* OpLabel        */
     {253, 1, ""},     /* OpReturn       */
 };
-#define ORC_OPNAME 5u
 
 static const orc_inst *lookup(uint32_t opcode) {
   for (size_t i = 0; i < sizeof(GRAMMAR) / sizeof(GRAMMAR[0]); ++i)
     if (GRAMMAR[i].opcode == opcode) return &GRAMMAR[i];
   return NULL;
+}
+
+/* Operand words before the string of a variable instruction (OpName 1,
+ * OpEntryPoint 2); for a fixed one, all of its operand words. */
+static uint32_t fixed_operands(const orc_inst *g) {
+  uint32_t k = 0;
+  while (g->roles[k] != '\0' && g->roles[k] != 'S') ++k;
+  return k;
 }
 
 /* A literal string is stored as bytes little-endian within each word, ends
@@ -130,21 +142,20 @@ static int contains(const uint32_t *sorted, uint64_t n, uint32_t v) {
 
 /* Module-level rules (section "Validation Rules"), a stage after the
  * semantic one for a module that passed it: the module must declare a
- * capability (OpCapability, 17), define its memory model (OpMemoryModel, 14)
- * and declare a function (OpFunction, 54).  The fourth rule of that section,
- * an entry point, needs OpEntryPoint (15), which is outside the twelve-opcode
- * grammar: a module holding one has already failed the parse stage, so the
- * rule is not checked here.  Returns the missing rules as 8 (capability) |
- * 16 (memory model) | 32 (function). */
+ * capability (OpCapability, 17), define its memory model (OpMemoryModel, 14),
+ * declare a function (OpFunction, 54) and declare an entry point
+ * (OpEntryPoint, 15).  Returns the missing rules as 8 (capability) | 16
+ * (memory model) | 32 (function) | 64 (entry point). */
 static uint32_t missing_rules(const uint32_t *w, uint64_t n) {
-  int capability = 0, memory_model = 0, function = 0;
+  int capability = 0, memory_model = 0, function = 0, entry_point = 0;
   for (uint64_t p = 5; p < n; p += w[p] >> 16) {
     uint32_t op = w[p] & 0xFFFFu;
     if (op == 17) capability = 1;
     if (op == 14) memory_model = 1;
     if (op == 54) function = 1;
+    if (op == 15) entry_point = 1;
   }
-  return (capability ? 0u : 8u) | (memory_model ? 0u : 16u) | (function ? 0u : 32u);
+  return (capability ? 0u : 8u) | (memory_model ? 0u : 16u) | (function ? 0u : 32u) | (entry_point ? 0u : 64u);
 }
 
 /* Decode (and, if semantic != 0, validate) one module w[0..n).  Instruction
@@ -191,9 +202,9 @@ static int check_module(const uint32_t *w, uint64_t n, int semantic, int rules, 
     uint32_t code = ORC_OK;
     if (wc == 0 || p + wc > n) code = ORC_BAD_WORD_COUNT;
     else if (g == NULL) code = ORC_UNKNOWN_OPCODE;
-    else if ((g->word_count != 0 && wc != g->word_count) || (g->word_count == 0 && wc < 3))
+    else if ((g->word_count != 0 && wc != g->word_count) || (g->word_count == 0 && wc < 2 + fixed_operands(g)))
       code = ORC_BAD_WORD_COUNT;
-    else if (op == ORC_OPNAME && !string_ok(w + p + 2, wc - 2))
+    else if (g->word_count == 0 && !string_ok(w + p + 1 + fixed_operands(g), wc - 1 - fixed_operands(g)))
       code = ORC_BAD_STRING;
     if (code != ORC_OK) {
       r->code = code;
@@ -273,8 +284,10 @@ int oracle_validate(const uint32_t *words, const int64_t *mod_off, int64_t n_mod
 }
 
 /* Records mode of the disassembler: for each instruction of the valid prefix
- * of each module, its opcode, its non-string operand words and the bytes of
- * its string (excluding the NUL).  Output arrays are sized by the caller for
+ * of each module (none when the header check failed; the instructions before
+ * the failing one when the parse stage failed; all of them otherwise), its
+ * opcode, its non-string operand words and the bytes of its string
+ * (excluding the NUL).  Output arrays are sized by the caller for
  * the whole batch (n_words entries each is always enough); rec_mod_off gets
  * the record CSR (n_modules+1).  Returns 0, or -1 on bad offsets. */
 int oracle_records(const uint32_t *words, const int64_t *mod_off, int64_t n_modules, uint16_t *op_out,
@@ -294,10 +307,12 @@ int oracle_records(const uint32_t *words, const int64_t *mod_off, int64_t n_modu
       uint64_t p = 5;
       for (uint32_t j = 0; j < r.n_inst; ++j) {
         uint32_t wc = w[p] >> 16, op = w[p] & 0xFFFFu;
+        const orc_inst *g = lookup(op);
         op_out[nr] = (uint16_t)op;
-        if (op == ORC_OPNAME) {
-          opnd[no++] = w[p + 1];
-          const uint8_t *bytes = (const uint8_t *)(w + p + 2);
+        if (g != NULL && g->word_count == 0) {
+          uint32_t k = fixed_operands(g);
+          for (uint32_t s = 1; s <= k; ++s) opnd[no++] = w[p + s];
+          const uint8_t *bytes = (const uint8_t *)(w + p + 1 + k);
           for (uint64_t i = 0; bytes[i] != 0; ++i) chars[nc++] = bytes[i];
         } else {
           for (uint32_t s = 1; s < wc; ++s) opnd[no++] = w[p + s];
@@ -344,7 +359,8 @@ int64_t oracle_encode(const uint16_t *op, const int32_t *opnd_off, const uint32_
       int64_t n_chars = str_off[j + 1] - str_off[j];
       uint64_t wc = 0;
       if (g == NULL) code = ORC_ENC_UNKNOWN_OPCODE;
-      else if ((g->word_count == 0 && n_ops != 1) || (g->word_count != 0 && n_ops != g->word_count - 1))
+      else if ((g->word_count == 0 && n_ops != (int64_t)fixed_operands(g)) ||
+               (g->word_count != 0 && n_ops != g->word_count - 1))
         code = ORC_ENC_OPERAND_COUNT;
       else if (g->word_count != 0 && n_chars != 0) code = ORC_ENC_BAD_STRING;
       else if (g->word_count == 0 && memchr(chars + str_off[j], 0, (size_t)n_chars) != NULL)

@@ -16,10 +16,12 @@ from collections import Counter
 
 # opcode -> (operand kinds after the first word); "str" marks a literal string
 # running to the end of the instruction.  Fixed-size instructions have exactly
-# len(kinds) operand words.
+# len(kinds) operand words.  OpEntryPoint's name is its last operand here: the
+# interface IDs SPIR-V allows after it are outside this contract.
 KINDS = {
     5: ("id", "str"),                       # OpName target, name
     14: ("lit", "lit"),                     # OpMemoryModel addressing, memory
+    15: ("lit", "id", "str"),               # OpEntryPoint model, function, name
     17: ("lit",),                           # OpCapability
     21: ("result", "lit", "lit"),           # OpTypeInt result, width, signedness
     43: ("id", "result", "lit"),            # OpConstant type, result, value
@@ -42,9 +44,9 @@ def _string_words_ok(raw: bytes) -> bool:
     return nul >= len(raw) - 4 and raw[nul:] == b"\x00" * (len(raw) - nul)
 
 
-# module-level rules (section "Validation Rules") checkable with the twelve
-# opcodes: mask bit of each rule -> the opcodes that satisfy it
-RULES = {8: {17}, 16: {14}, 32: {54}}   # a capability, the memory model, a function
+# module-level rules (section "Validation Rules"): mask bit of each rule ->
+# the opcodes that satisfy it
+RULES = {8: {17}, 16: {14}, 32: {54}, 64: {15}}   # capability, memory model, function, entry point
 
 
 def check(words, semantic: bool = True, rules: bool = False):
@@ -73,9 +75,10 @@ def check(words, semantic: bool = True, rules: bool = False):
             return (6, 0, pos, len(insts), insts)
         kinds = KINDS[opcode]
         if "str" in kinds:
-            if count < 2 + 1:
+            head = kinds.index("str")  # operand words before the string
+            if count < 1 + head + 1:
                 return (5, 0, pos, len(insts), insts)
-            if not _string_words_ok(raw[4 * (pos + 2):4 * end]):
+            if not _string_words_ok(raw[4 * (pos + 1 + head):4 * end]):
                 return (7, 0, pos, len(insts), insts)
         elif count != 1 + len(kinds):
             return (5, 0, pos, len(insts), insts)
@@ -118,7 +121,7 @@ def encode_module(records, version_word=0x00010600, generator_word=0):
             return (1, j)
         kinds = KINDS[opcode]
         is_name = "str" in kinds
-        want = 1 if is_name else len(kinds)
+        want = kinds.index("str") if is_name else len(kinds)
         if len(operands) != want:
             return (2, j)
         if (not is_name and len(name) > 0) or (is_name and b"\x00" in name):

@@ -14,7 +14,11 @@ out once per module, sequentially, as the paper's module-level ID allocation
 does (section "Enabling Function Composition", SSA paragraph).
 
 Module recipe (every draw from ``numpy.random.default_rng(seed)``, PCG64):
-  * prologue: OpCapability Kernel(6); OpMemoryModel 2 2; OpTypeInt %1 32 0;
+  * prologue: OpCapability Kernel(6); OpMemoryModel 2 2; OpEntryPoint
+    Kernel(6) %2 "main"; OpTypeInt %1 32 0; OpFunction %1 %2 0 %1 (so every
+    module meets the four module-level rules: a capability, the memory model,
+    a function and an entry point; the entry point names the function that
+    the prologue defines next);
   * then i.i.d. opcodes from MIX (percent); a U (ID-use) slot draws uniformly
     from the results defined so far; D (result) slots are sequential from 1;
   * literals: OpCapability in {4,5,6,11,39}, OpMemoryModel (2,2), OpTypeInt
@@ -35,9 +39,9 @@ import numpy as np
 MAGIC = 0x07230203
 VERSION_1_6 = 0x00010600
 
-# name, opcode, fixed word count (0: OpName, 2 + string words), operand roles
-# after the first word (U: ID use, D: result ID, L: literal, S: string words),
-# mix percent.
+# name, opcode, fixed word count (0: variable, the operands before S and then
+# the string words), operand roles after the first word (U: ID use, D: result
+# ID, L: literal, S: string words), mix percent.
 OPS = [
     ("OpCapability", 17, 2, "L", 1),
     ("OpMemoryModel", 14, 3, "LL", 1),
@@ -51,8 +55,14 @@ OPS = [
     ("OpIAdd", 128, 5, "UDUU", 27),
     ("OpReturn", 253, 1, "", 3),
     ("OpFunctionEnd", 56, 1, "", 3),
+    # prologue only (weight 0): execution model, entry function, name
+    ("OpEntryPoint", 15, 0, "LUS", 0),
 ]
-K_CAP, K_MEM, K_NAME, K_TYPEINT, K_CONST, K_FUNC, K_LABEL, K_LOAD, K_STORE, K_IADD, K_RET, K_FEND = range(12)
+(K_CAP, K_MEM, K_NAME, K_TYPEINT, K_CONST, K_FUNC, K_LABEL, K_LOAD, K_STORE, K_IADD, K_RET, K_FEND,
+ K_ENTRY) = range(13)
+PROLOGUE = (K_CAP, K_MEM, K_ENTRY, K_TYPEINT, K_FUNC)
+N_PROLOGUE = len(PROLOGUE)
+ENTRY_NAME = b"main"
 OPCODE = np.array([o[1] for o in OPS], dtype=np.int64)
 FIXED_WC = np.array([o[2] for o in OPS], dtype=np.int64)
 ROLES = [o[3] for o in OPS]
@@ -106,20 +116,22 @@ def _segment_arange(lengths: np.ndarray) -> np.ndarray:
 
 
 def gen_module(seed, n_inst: int) -> Module:
-    """Generate one module of ``n_inst`` (>= 3) instructions."""
-    if n_inst < 3:
-        raise ValueError("a generated module has at least the 3 prologue instructions")
+    """Generate one module of ``n_inst`` (>= 5) instructions."""
+    if n_inst < N_PROLOGUE:
+        raise ValueError(f"a generated module has at least the {N_PROLOGUE} prologue instructions")
     rng = np.random.default_rng(seed)
     n = int(n_inst)
     kind = np.empty(n, dtype=np.int8)
-    kind[0], kind[1], kind[2] = K_CAP, K_MEM, K_TYPEINT
-    kind[3:] = rng.choice(len(OPS), size=n - 3, p=MIX)
+    kind[:N_PROLOGUE] = PROLOGUE
+    kind[N_PROLOGUE:] = rng.choice(len(OPS), size=n - N_PROLOGUE, p=MIX)
 
     is_name = kind == K_NAME
     n_names = int(is_name.sum())
     name_len = rng.integers(4, 25, size=n_names)
     wc = FIXED_WC[kind].copy()
     wc[is_name] = 2 + name_len // 4 + 1
+    entry = 2  # index of the prologue's OpEntryPoint
+    wc[entry] = 3 + len(ENTRY_NAME) // 4 + 1
 
     has_def = HAS_DEF[kind]
     defs_incl = np.cumsum(has_def, dtype=np.int64)
@@ -140,8 +152,11 @@ def gen_module(seed, n_inst: int) -> Module:
             continue
         idx = np.nonzero(kind == k)[0]
         words[starts[idx] + 1 + r.index("D")] = defs_incl[idx].astype(np.uint32)
-    # ID uses: uniform over earlier results
+    # ID uses: uniform over earlier results (the entry point's function is
+    # the prologue's OpFunction, %2, defined after it)
     for k in range(len(OPS)):
+        if k == K_ENTRY:
+            continue
         for s, role in enumerate(ROLES[k]):
             if role != "U":
                 continue
@@ -150,6 +165,10 @@ def gen_module(seed, n_inst: int) -> Module:
                 continue
             v = rng.integers(1, results_before[idx] + 1)
             words[starts[idx] + 1 + s] = v.astype(np.uint32)
+    pe = int(starts[entry])
+    words[pe + 1] = 6  # execution model Kernel
+    words[pe + 2] = int(defs_incl[4])  # the prologue function's result ID
+    words.view(np.uint8)[4 * (pe + 3):4 * (pe + 3) + len(ENTRY_NAME)] = np.frombuffer(ENTRY_NAME, np.uint8)
     # literals
     cap_idx = np.nonzero(kind == K_CAP)[0]
     caps = CAPABILITIES[rng.integers(0, len(CAPABILITIES), size=cap_idx.size)]
@@ -174,17 +193,21 @@ def gen_module(seed, n_inst: int) -> Module:
     byte_pos = np.repeat(4 * (starts[name_idx] + 2), name_len) + _segment_arange(name_len)
     words.view(np.uint8)[byte_pos] = chars
 
-    # records: opcode, non-string operand words, string bytes
+    # records: opcode, non-string operand words, string bytes (the entry
+    # point's name comes first: no OpName precedes it)
     n_ops = np.where(is_name, 1, wc - 1).astype(np.int64)
+    n_ops[entry] = 2
     opnd_off = np.concatenate([[0], np.cumsum(n_ops)]).astype(np.int32)
     opnd_pos = np.repeat(starts + 1, n_ops) + _segment_arange(n_ops)
     opnd = words[opnd_pos].copy()
     str_len = np.zeros(n, dtype=np.int64)
     str_len[is_name] = name_len
+    str_len[entry] = len(ENTRY_NAME)
     str_off = np.concatenate([[0], np.cumsum(str_len)]).astype(np.int32)
+    rec_chars = np.concatenate([np.frombuffer(ENTRY_NAME, np.uint8), chars])
     return Module(words=words, kind=kind, wc=wc, starts=starts, n_results=n_results, bound=bound,
                   rec_op=OPCODE[kind].astype(np.uint16), rec_opnd_off=opnd_off, rec_opnd=opnd,
-                  rec_str_off=str_off, rec_chars=chars.copy())
+                  rec_str_off=str_off, rec_chars=rec_chars)
 
 
 # ----------------------------------------------------------------------------
@@ -199,7 +222,7 @@ def _slot_positions(mod: Module, role: str, post_prologue: bool = True):
                 continue
             idx = np.nonzero(mod.kind == k)[0]
             if post_prologue:
-                idx = idx[idx >= 3]
+                idx = idx[idx >= N_PROLOGUE]
             inst.append(idx)
             pos.append(mod.starts[idx] + 1 + s)
     if not inst:
@@ -212,7 +235,7 @@ def _slot_positions(mod: Module, role: str, post_prologue: bool = True):
 
 def inject_bad_wc(mod: Module, rng) -> Module:
     """A post-prologue fixed-length instruction gets word count +-1."""
-    cand = np.nonzero((np.arange(mod.n_inst) >= 3) & (mod.kind != K_NAME))[0]
+    cand = np.nonzero((np.arange(mod.n_inst) >= N_PROLOGUE) & (mod.kind != K_NAME))[0]
     i = int(cand[rng.integers(0, cand.size)])
     delta = 1 if rng.integers(0, 2) else -1
     p = int(mod.starts[i])
@@ -243,7 +266,7 @@ def inject_dup(mod: Module, rng) -> Module:
     p = int(dpos[rng.integers(0, dpos.size)])
     w = mod.words.copy()
     displaced = int(w[p])
-    new = int(rng.integers(1, displaced))  # displaced >= 2 after the prologue
+    new = int(rng.integers(1, displaced))  # displaced >= 3 after the prologue
     w[p] = np.uint32(new)
     _, upos = _slot_positions(mod, "U", post_prologue=False)
     used = bool(np.any(w[upos] == displaced))
@@ -332,7 +355,7 @@ def config4(n_records: int = 10_000_000, n_modules: int = 1024):
     Module m gets floor((m+1)N/M) - floor(mN/M) records and its own ID space
     (content seed [4, m])."""
     bounds = [(m * n_records) // n_modules for m in range(n_modules + 1)]
-    mods = [gen_module([4, m], max(3, bounds[m + 1] - bounds[m])) for m in range(n_modules)]
+    mods = [gen_module([4, m], max(N_PROLOGUE, bounds[m + 1] - bounds[m])) for m in range(n_modules)]
     return mods, pack_records(mods)
 
 

@@ -38,10 +38,24 @@ def test_sequential_results_and_backward_uses():
                 defs.append(int(m.words[m.starts[i] + 1 + s]))
             elif role == "U":
                 v = int(m.words[m.starts[i] + 1 + s])
-                assert 1 <= v <= len(defs)  # refers to an earlier result
+                if m.kind[i] == spvgen.K_ENTRY:
+                    assert v == 2  # the prologue's function, defined right after
+                else:
+                    assert 1 <= v <= len(defs)  # refers to an earlier result
                 uses.append(v)
     assert defs == list(range(1, len(defs) + 1))
     assert m.n_results == len(defs)
+
+
+def test_prologue():
+    """Capability, memory model, entry point naming the function %2, %1 =
+    OpTypeInt 32 0, %2 = OpFunction %1 None %1."""
+    m = spvgen.gen_module(12, 50)
+    w = [int(x) for x in m.words[5:5 + 2 + 3 + 5 + 4 + 5]]
+    assert w == [0x00020011, 6, 0x0003000E, 2, 2, 0x0005000F, 6, 2, 0x6E69616D, 0,
+                 0x00040015, 1, 32, 0, 0x00050036, 1, 2, 0, 1]
+    assert list(m.rec_op[:5]) == [17, 14, 15, 21, 54]
+    assert bytes(m.rec_chars[:4]) == b"main" and m.rec_str_off[3] == 4
 
 
 def test_strings_nul_terminated_and_padded():

@@ -141,13 +141,38 @@ def test_bruteforce_encode():
             assert code[i] == 0 and [int(x) for x in w[wmo[i]:wmo[i + 1]]] == exp, recs
 
 
+def _rule_subset_modules():
+    """Every subset of the four rule opcodes (capability, memory model,
+    function, entry point) in several orders, around an OpTypeInt %1; the
+    function is %2 = OpFunction %1 None %1 and the entry point names %2 when
+    the function is present, else %1 (the rules do not look at its type)."""
+    rng = np.random.default_rng(674)
+    mods = []
+    for bits in range(16):
+        has = [bool(bits >> k & 1) for k in range(4)]
+        parts = [[4 << 16 | 21, 1, 32, 0]]
+        if has[0]:
+            parts.append([2 << 16 | 17, 6])
+        if has[1]:
+            parts.append([3 << 16 | 14, 2, 2])
+        if has[2]:
+            parts.append([5 << 16 | 54, 1, 2, 0, 1])
+        if has[3]:
+            parts.append([5 << 16 | 15, 6, 2 if has[2] else 1, 0x6E69616D, 0])
+        for _ in range(4):
+            order = rng.permutation(len(parts))
+            body = [w for i in order for w in parts[i]]
+            mods.append([0x07230203, 0x00010600, 0, 3 if has[2] else 2, 0] + body)
+    return mods
+
+
 def test_bruteforce_module_rules():
-    """With the module-level rules: every presence pattern of the three rule
-    opcodes occurs among sequences of up to three instructions."""
-    mods = _modules()
+    """With the module-level rules: every presence pattern of the four rule
+    opcodes, against the independent checker."""
+    mods = _modules() + _rule_subset_modules()
     res = _compare(mods, True, rules=True)
     rules = res["code"] == oracle.E_MODULE_RULES
-    assert set(int(x) for x in np.unique(res["sem_mask"][rules])) == {8, 16, 24, 32, 40, 48, 56}
+    assert set(int(x) for x in np.unique(res["sem_mask"][rules])) == set(range(8, 128, 8))
     assert int(np.sum(res["code"] == 0)) > 0
     # without the rules the same modules keep their codes, except that rule
     # failures read as valid

@@ -13,6 +13,7 @@ import pytest
 import oracle
 import test_oracle_bruteforce as brute
 import test_oracle_pins as pins
+import test_oracle_rules as rules
 from conftest import parse_golden, ROOT
 
 SRC = os.path.join(ROOT, "oracle", "oracle.c")
@@ -31,7 +32,17 @@ MUTANTS = [
     ("padding not checked", "if (((w[b / 4] >> (8 * (b % 4))) & 0xFFu) != 0) return 0;", ";"),
     ("OpLoad roles transposed", '{61, 4, "UDU"}', '{61, 4, "UUD"}'),
     ("OpIAdd result slot", '{128, 5, "UDUU"}', '{128, 5, "DUUU"}'),
-    ("OpName minimum count", "(g->word_count == 0 && wc < 3)", "(g->word_count == 0 && wc < 2)"),
+    ("string minimum count", "(g->word_count == 0 && wc < 2 + fixed_operands(g))",
+     "(g->word_count == 0 && wc < 1 + fixed_operands(g))"),
+    ("string always after word 2", "!string_ok(w + p + 1 + fixed_operands(g), wc - 1 - fixed_operands(g))",
+     "!string_ok(w + p + 2, wc - 2)"),
+    ("OpEntryPoint function not an ID", '{15, 0, "LUS"}', '{15, 0, "LLS"}'),
+    ("entry-point rule dropped", "if (op == 15) entry_point = 1;", "entry_point = 1;"),
+    ("function rule reads the memory model", "if (op == 54) function = 1;", "if (op == 14) function = 1;"),
+    ("records include the failing instruction", "for (uint32_t j = 0; j < r.n_inst; ++j) {",
+     "for (uint32_t j = 0; j < r.n_inst + (r.code >= ORC_BAD_WORD_COUNT && r.code <= ORC_BAD_STRING); ++j) {"),
+    ("records of header failures", "if (r.code == ORC_OK || r.code >= ORC_BAD_WORD_COUNT) {",
+     "if (r.code == ORC_OK || r.code >= ORC_BAD_WORD_COUNT || r.code == ORC_BAD_VERSION) {\n      if (r.code == ORC_BAD_VERSION) r.n_inst = 1;"),
     ("index off by one", "if (idx_off) idx_off[k] = (uint32_t)p;", "if (idx_off) idx_off[k] = (uint32_t)p + 1;"),
     ("n_inst at error", "r->err_word = (uint32_t)p;\n      r->n_inst = (uint32_t)k;",
      "r->err_word = (uint32_t)p;\n      r->n_inst = (uint32_t)k + 1;"),
@@ -61,6 +72,9 @@ def _battery():
         ("encode sizes", pins.test_encode_sizes),
         ("brute force", brute.test_bruteforce_small_modules),
         ("brute encode", brute.test_bruteforce_encode),
+        ("brute rules", brute.test_bruteforce_module_rules),
+        ("records of failing modules", pins.test_records_of_failing_modules),
+        ("rules: earlier stages", rules.test_earlier_stages_win),
     ]
     import inspect
     rule_cases = [m.args for m in pins.test_rules.pytestmark if m.name == "parametrize"][0][1]
@@ -68,6 +82,11 @@ def _battery():
         checks.append((f"rule {words[:6]}", lambda w=words, e=expect: pins.test_rules(w, e)))
     for rec, code in [m.args for m in pins.test_encode_failures.pytestmark if m.name == "parametrize"][0][1]:
         checks.append((f"enc {rec[0]}", lambda r=rec, c=code: pins.test_encode_failures(r, c)))
+    for parts, expect in [m.args for m in rules.test_rules_on_valid_modules.pytestmark
+                          if m.name == "parametrize"][0][1]:
+        checks.append((f"rules {len(parts)}", lambda p=parts, e=expect: rules.test_rules_on_valid_modules(p, e)))
+    for ent, expect in [m.args for m in rules.test_entry_point_forms.pytestmark if m.name == "parametrize"][0][1]:
+        checks.append((f"entry {ent[0]:#x}", lambda a=ent, e=expect: rules.test_entry_point_forms(a, e)))
     for name, fn in checks:
         try:
             fn()

@@ -41,7 +41,7 @@ def test_paper_examples_decode(golden_cases):
         pos = 5
         for j, r in enumerate(case["recs"]):
             assert io[j] == pos
-            pos += 1 + len(r[1]) + ((len(r[2]) // 4 + 1) if r[0] == 5 else 0)
+            pos += 1 + len(r[1]) + ((len(r[2]) // 4 + 1) if r[0] in (5, 15) else 0)
         rec = oracle.records(w, [0, w.size])
         assert [int(x) for x in rec["opnd"]] == [v for r in case["recs"] for v in r[1]]
         assert bytes(rec["chars"]) == b"".join(r[2] for r in case["recs"])
@@ -49,7 +49,7 @@ def test_paper_examples_decode(golden_cases):
 
 def test_generator_layout_pins_index():
     """starts == 5 + exclusive cumsum of the generator's own word counts."""
-    for seed, n in [(1, 10_000), (5, 777), (9, 3)]:
+    for seed, n in [(1, 10_000), (5, 777), (9, 5)]:
         m = spvgen.gen_module(seed, n)
         res, io, iop = oracle.validate(m.words, [0, m.words.size])
         assert res[0]["code"] == 0 and res[0]["sem_mask"] == 0 and res[0]["n_inst"] == n
@@ -90,7 +90,7 @@ def test_semantic_against_numpy_sets():
     rng = np.random.default_rng(123)
     seen = set()
     for trial in range(120):
-        m = spvgen.gen_module([77, trial], int(rng.integers(3, 400)))
+        m = spvgen.gen_module([77, trial], int(rng.integers(5, 400)))
         dpos, upos = _id_slots(m)
         w = m.words.copy()
         allpos = np.concatenate([dpos, upos])
@@ -117,7 +117,7 @@ def test_semantic_against_numpy_sets():
 
 def test_round_trip_identity():
     """encode(records(decode(w))) == w and decode(encode(r)) == r."""
-    mods = [spvgen.gen_module([8, i], n) for i, n in enumerate([3, 10, 100, 2_500])]
+    mods = [spvgen.gen_module([8, i], n) for i, n in enumerate([5, 10, 100, 2_500])]
     b = spvgen.pack(mods)
     rec = oracle.records(b.words, b.mod_off)
     w, wmo, code, bad = oracle.encode(rec["op"], rec["opnd_off"], rec["opnd"], rec["str_off"], rec["chars"],
@@ -169,6 +169,44 @@ HDR = [0x07230203, 0x00010600, 0, 10, 0]
 def test_rules(words, expect):
     res = oracle.validate(np.array(words, np.uint32), [0, len(words)], index=False)
     assert tuple(int(res[0][k]) for k in ("code", "sem_mask", "err_word", "n_inst")) == expect
+
+
+def test_records_of_failing_modules():
+    """Records mode keeps each module's valid instruction prefix: none when
+    the header check fails, the instructions before the failing one when the
+    parse stage fails, every instruction when only the semantic stage fails.
+    Hand-written words; the expected records are read off them."""
+    LBL = [0x000200F8, 1]                              # %1 = OpLabel
+    ENT = [0x0005000F, 6, 1, 0x6E69616D, 0]            # OpEntryPoint Kernel %1 "main"
+    mods = [
+        [0x07230203, 0x00010700, 0, 5, 0] + LBL,       # minor 7: header fails
+        [0x07230203, 0x00010600, 0],                   # truncated header
+        HDR + LBL + [0x00020063, 1] + LBL,             # unknown opcode 99 second
+        HDR + [0x00020011, 6, 0x00030011, 6, 7] + LBL,  # OpCapability with 3 words second
+        HDR + LBL + [0x00030005, 1, 0x64636261] + LBL,  # OpName without terminator second
+        HDR + [0x00030011, 6] + LBL,                   # first instruction overruns into the next one
+        HDR + LBL + LBL,                               # %1 defined twice: semantic only
+        HDR + ENT + LBL,                               # valid, with an entry point
+    ]
+    sizes = np.array([len(m) for m in mods], np.int64)
+    mod_off = np.concatenate([[0], np.cumsum(sizes)])
+    words = np.array([x for m in mods for x in m], np.uint32)
+    expect = [[], [], [(248, [1], b"")], [(17, [6], b"")], [(248, [1], b"")],
+              [(17, [6, 0x000200F8], b"")][:0], [(248, [1], b""), (248, [1], b"")],
+              [(15, [6, 1], b"main"), (248, [1], b"")]]
+    rec = oracle.records(words, mod_off)
+    got = []
+    for m in range(len(mods)):
+        out = []
+        for r in range(int(rec["rec_mod_off"][m]), int(rec["rec_mod_off"][m + 1])):
+            a, b = int(rec["opnd_off"][r]), int(rec["opnd_off"][r + 1])
+            c, d = int(rec["str_off"][r]), int(rec["str_off"][r + 1])
+            out.append((int(rec["op"][r]), [int(x) for x in rec["opnd"][a:b]], bytes(rec["chars"][c:d])))
+        got.append(out)
+    assert got == expect
+    res = oracle.validate(words, mod_off, index=False)
+    assert [int(x) for x in res["code"]] == [3, 1, 6, 5, 7, 5, 9, 0]
+    assert [int(x) for x in res["n_inst"]] == [len(e) for e in expect]
 
 
 def test_decode_has_no_semantic_stage():
