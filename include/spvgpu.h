@@ -54,8 +54,8 @@ extern "C" {
  *   parse  : walk from word 5; at each instruction start p, in this order:
  *            word count 0 or past the module end -> BAD_WORD_COUNT; opcode
  *            not in the grammar table -> UNKNOWN_OPCODE; word count not the
- *            table's -> BAD_WORD_COUNT; OpName string not NUL-terminated in
- *            its last word with zero padding -> BAD_STRING.  err_word = p
+ *            table's -> BAD_WORD_COUNT; string (OpName, OpEntryPoint) not
+ *            NUL-terminated in its last word with zero padding -> BAD_STRING.  err_word = p
  *            (word offset in the module), n_inst = instructions before p.
  *   semantic (validate only): over ID-role words, id == 0 or id >= bound ->
  *            OOB (mask 1); a result ID defined twice -> DUP (mask 2); an ID
@@ -75,9 +75,8 @@ extern "C" {
 #define SPV_E_UNDEFINED_ID 10
 /* (spv_validate with SPV_OPT_MODULE_RULES) a module that passed every check
  * above lacks what section "Validation Rules" requires of every module:
- * sem_mask = 8 no OpCapability | 16 no OpMemoryModel | 32 no OpFunction.
- * The section's entry-point rule is not checked: OpEntryPoint is outside the
- * grammar table, so a module holding one fails with UNKNOWN_OPCODE first. */
+ * sem_mask = 8 no OpCapability | 16 no OpMemoryModel | 32 no OpFunction |
+ * 64 no OpEntryPoint. */
 #define SPV_E_MODULE_RULES 11
 
 /* spv_validate option: hold modules that pass every check to the
@@ -87,8 +86,8 @@ extern "C" {
 /* ---- encode status codes (per module) ---------------------------------- */
 #define SPV_ENC_OK 0
 #define SPV_ENC_UNKNOWN_OPCODE 1 /* opcode not in the grammar table */
-#define SPV_ENC_OPERAND_COUNT 2  /* non-string operand count differs from the table (OpName: 1) */
-#define SPV_ENC_BAD_STRING 3     /* string on a non-OpName record, or NUL inside an OpName string */
+#define SPV_ENC_OPERAND_COUNT 2  /* non-string operand count differs from the table (OpName 1, OpEntryPoint 2) */
+#define SPV_ENC_BAD_STRING 3     /* string on a record without a string operand, or a NUL inside a string */
 #define SPV_ENC_TOO_LONG 4       /* word count would exceed 65535 */
 #define SPV_ENC_BAD_ID 5         /* an ID operand equals 0xFFFFFFFF (bound not representable) */
 #define SPV_ENC_CAPACITY 6       /* the module would end past words_cap (its words are not kept) */
@@ -99,10 +98,12 @@ extern "C" {
  * are then not valid and the call may be repeated. */
 #define SPV_E_SPIN_LIMIT 0xDEAD
 
-/* Grammar table (the twelve opcodes of the synthetic workloads): opcode,
- * word count, operand roles (U = ID use, D = result ID, L = literal,
- * S = string words):
- *   OpName 5 (>=3, U S...), OpMemoryModel 14 (3, L L), OpCapability 17
+/* Grammar table (the twelve opcodes of the synthetic workloads and
+ * OpEntryPoint): opcode, word count, operand roles (U = ID use, D = result
+ * ID, L = literal, S = string words):
+ *   OpName 5 (>=3, U S...), OpMemoryModel 14 (3, L L), OpEntryPoint 15
+ *   (>=4, L U S...; its string must end in its last word: the interface IDs
+ *   SPIR-V allows after the name are not part of this table), OpCapability 17
  *   (2, L), OpTypeInt 21 (4, D L L), OpConstant 43 (4, U D L), OpFunction
  *   54 (5, U D L U), OpFunctionEnd 56 (1), OpLoad 61 (4, U D U), OpStore 62
  *   (3, U U), OpIAdd 128 (5, U D U U), OpLabel 248 (2, D), OpReturn 253 (1). */
@@ -175,8 +176,9 @@ int spv_records_workspace_size(spv_ctx *ctx, int64_t n_modules, int64_t n_words,
  * its valid instruction prefix, results[m].n_inst of them, or none when its
  * header check failed (codes 1..4).  Record r: op[r] = its opcode; its
  * non-string operand words opnd[opnd_off[r] .. opnd_off[r+1]) (OpName: its
- * target ID); its string bytes chars[str_off[r] .. str_off[r+1]) (OpName:
- * the name up to, not including, its NUL; none otherwise).  rec_mod_off
+ * target ID; OpEntryPoint: execution model and function ID); its string bytes
+ * chars[str_off[r] .. str_off[r+1]) (OpName, OpEntryPoint: the name up to,
+ * not including, its NUL; none otherwise).  rec_mod_off
  * receives the records' CSR by module; the record count is
  * rec_mod_off[n_modules] (all -1 if a kernel's wait exceeded its spin limit).
  * For a valid module, spv_encode of its records gives its words back.
@@ -206,7 +208,8 @@ int spv_encode_workspace_size(spv_ctx *ctx, int64_t n_modules, int64_t n_records
  * none), schema 0).  Records are CSR by module: module m owns records
  * rec_mod_off[m] .. rec_mod_off[m+1]; record r has opcode op[r], operands
  * opnd[opnd_off[r] .. opnd_off[r+1]) and string bytes
- * chars[str_off[r] .. str_off[r+1]) (no NUL; only OpName may have one).
+ * chars[str_off[r] .. str_off[r+1]) (no NUL; only OpName and OpEntryPoint
+ * may have one).
  * A module with a failing record writes no words; enc_code[m] /
  * enc_bad_record[m] (module-relative index of its first failing record, -1
  * if none) say why.  word_mod_off (n_modules+1) receives the dense output

@@ -22,7 +22,7 @@ _lock = threading.Lock()
 OK, E_TRUNCATED_HEADER, E_BAD_MAGIC, E_BAD_VERSION, E_BAD_SCHEMA = 0, 1, 2, 3, 4
 E_BAD_WORD_COUNT, E_UNKNOWN_OPCODE, E_BAD_STRING = 5, 6, 7
 E_ID_OUT_OF_BOUND, E_DUPLICATE_ID, E_UNDEFINED_ID = 8, 9, 10
-E_MODULE_RULES = 11  # with rules: sem_mask = 8 no OpCapability | 16 no OpMemoryModel | 32 no OpFunction
+E_MODULE_RULES = 11  # with rules: sem_mask = 8 no OpCapability | 16 no OpMemoryModel | 32 no OpFunction | 64 no OpEntryPoint
 ENC_OK, ENC_UNKNOWN_OPCODE, ENC_OPERAND_COUNT, ENC_BAD_STRING, ENC_TOO_LONG, ENC_BAD_ID = range(6)
 
 RESULT_DTYPE = np.dtype([("code", "<u4"), ("sem_mask", "<u4"), ("err_word", "<u4"), ("n_inst", "<u4")])

@@ -26,7 +26,7 @@ ERRORS = {-1: "invalid argument", -2: "capacity", -3: "workspace", -4: "HIP erro
 OK, E_TRUNCATED_HEADER, E_BAD_MAGIC, E_BAD_VERSION, E_BAD_SCHEMA = 0, 1, 2, 3, 4
 E_BAD_WORD_COUNT, E_UNKNOWN_OPCODE, E_BAD_STRING = 5, 6, 7
 E_ID_OUT_OF_BOUND, E_DUPLICATE_ID, E_UNDEFINED_ID = 8, 9, 10
-E_MODULE_RULES = 11  # validate(module_rules=True): sem_mask = 8 no capability | 16 no memory model | 32 no function
+E_MODULE_RULES = 11  # validate(module_rules=True): sem_mask = 8 no capability | 16 no memory model | 32 no function | 64 no entry point
 OPT_MODULE_RULES = 1
 E_SPIN_LIMIT = 0xDEAD  # every result of a call whose inter-block wait gave up (repeat the call)
 ENC_OK, ENC_UNKNOWN_OPCODE, ENC_OPERAND_COUNT, ENC_BAD_STRING, ENC_TOO_LONG, ENC_BAD_ID, ENC_CAPACITY = range(7)
@@ -181,8 +181,10 @@ def _run(semantic: bool, words, mod_off, index: bool, ctx: Optional[Context], st
     ctx = ctx or context(words.device.index)
     W = int(words.numel())
     M = int(mod_off.numel()) - 1
-    assert words.is_cuda and mod_off.is_cuda and mod_off.dtype == torch.int64
-    assert words.dtype in (torch.int32, torch.uint32) and words.is_contiguous()
+    if not (words.is_cuda and mod_off.is_cuda and mod_off.dtype == torch.int64 and mod_off.is_contiguous()):
+        raise SpvError("words and mod_off must be CUDA tensors, mod_off contiguous int64")
+    if words.dtype not in (torch.int32, torch.uint32) or not words.is_contiguous():
+        raise SpvError("words must be a contiguous int32 / uint32 CUDA tensor")
     dev = words.device
     if out is None:
         results = torch.empty((M, 4), dtype=torch.int32, device=dev)
@@ -190,9 +192,22 @@ def _run(semantic: bool, words, mod_off, index: bool, ctx: Optional[Context], st
         idx_op = torch.empty(W if index else 0, dtype=torch.int16, device=dev) if index else None
     else:
         results, idx_off, idx_op = out
+        if (results.dtype not in (torch.int32, torch.uint32) or results.numel() < 4 * M
+                or not results.is_contiguous() or not results.is_cuda):
+            raise SpvError(f"results must be a contiguous int32 CUDA tensor of {M} rows of 4")
+        if index:
+            if idx_off is None or idx_op is None:
+                raise SpvError("index=True needs both idx_off and idx_op in out")
+            for t, dt in ((idx_off, (torch.int32, torch.uint32)), (idx_op, (torch.int16, torch.uint16))):
+                if t.dtype not in dt or not t.is_contiguous() or not t.is_cuda:
+                    raise SpvError("idx_off must be contiguous int32 and idx_op contiguous int16 CUDA tensors")
+        else:
+            idx_off = idx_op = None
+    # the library checks the capacity of the index buffers the caller gave
+    idx_cap = min(int(idx_off.numel()), int(idx_op.numel())) if index else 0
     ws_bytes = ctx.workspace_size(M, W)
     ws = workspace if workspace is not None else ctx.workspace(ws_bytes)
-    args = [ctx.h, _ptr(words), _ptr(mod_off), M, W, _ptr(idx_off), _ptr(idx_op), W if index else 0,
+    args = [ctx.h, _ptr(words), _ptr(mod_off), M, W, _ptr(idx_off), _ptr(idx_op), idx_cap,
             _ptr(results)]
     if semantic:
         rc = ctx.lib.spv_validate(*args, flags, _ptr(ws), ws.numel(), _stream(stream))

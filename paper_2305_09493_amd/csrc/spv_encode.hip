@@ -35,9 +35,11 @@ struct EGEnt {
   uint8_t idmask;  // operand s (0-based) is an ID (use or result) when bit s is set
   uint8_t is_name;
 };
-__device__ __constant__ EGEnt kEncGrammar[12] = {
+constexpr int kEncOps = 13;
+__device__ __constant__ EGEnt kEncGrammar[kEncOps] = {
     {5, 1, 0x1, 1},    // OpName          id, string
     {14, 2, 0x0, 0},   // OpMemoryModel
+    {15, 2, 0x2, 1},   // OpEntryPoint    execution model, function, string
     {17, 1, 0x0, 0},   // OpCapability
     {21, 3, 0x1, 0},   // OpTypeInt       result, width, signedness
     {43, 3, 0x3, 0},   // OpConstant      type, result, value
@@ -51,11 +53,11 @@ __device__ __constant__ EGEnt kEncGrammar[12] = {
 };
 
 // packed LDS table entry for opcode < 256: bit 15 known, bits 0..3 n_ops,
-// bits 4..7 ID mask, bit 8 OpName
+// bits 4..7 ID mask, bit 8 string operand (OpName, OpEntryPoint)
 __device__ __forceinline__ void enc_table(uint16_t* tbl) {
   for (int i = threadIdx.x; i < 257; i += blockDim.x) tbl[i] = 0;
   __syncthreads();
-  if (threadIdx.x < 12) {
+  if (threadIdx.x < kEncOps) {
     EGEnt g = kEncGrammar[threadIdx.x];
     tbl[g.op] = uint16_t(0x8000u | g.n_ops | (uint32_t(g.idmask) << 4) | (uint32_t(g.is_name) << 8));
   }

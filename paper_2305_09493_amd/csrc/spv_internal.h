@@ -133,7 +133,8 @@ enum {
 constexpr uint32_t kModeResolved = 1u;
 // per-tile summary of the chain pass (4 words): word 0 = exit offset (bits
 // 0..7) | flags, word 1 = candidate chain of lane 0 before its first module
-// start, word 2 = starts of the module open at the tile start (lane 0's
+// start (bits 0..15: its plausible nodes; bits 16..31: the invalid node that
+// ends it, if any), word 2 = starts of the module open at the tile start (lane 0's
 // entry-dependent ones excluded), word 3 = starts after the tile's last
 // module start
 constexpr uint32_t kSumFallback = 1u << 31, kSumModStart = 1u << 30, kSumReset = 1u << 29;
@@ -180,6 +181,7 @@ struct VParams {
 // A word w at a candidate start is a plausible instruction iff
 // (wc - lo) < n_ok (unsigned) with wc = w >> 16.
 constexpr int kOpName = 5;
+constexpr int kOpEntryPoint = 15;
 
 struct Params;  // forward
 

@@ -11,7 +11,7 @@
 // or none when its header check failed.
 //
 // How: one scan over the modules gives each module's first record; a count
-// pass gives every record's operand and character counts (an OpName string
+// pass gives every record's operand and character counts (a string
 // was validated by decode, so its length follows from its last word alone)
 // and the totals of blocks of 1024 records; a scan of those totals and an
 // in-block scan in the scatter give both offset arrays while it writes the
@@ -68,18 +68,26 @@ __device__ __forceinline__ RecInst rec_inst(const RParams& P, int64_t r) {
   return ri;
 }
 
-// Operand words and string bytes of a record.  OpName: one operand (its
-// target) and the string, whose first NUL lies in its last word (decode
-// checked that), so its length is 4 * (string words - 1) plus the bytes of
-// the last word before the NUL.
+// Operand words before the string of a string-bearing instruction (OpName:
+// its target; OpEntryPoint: execution model and entry function), 0 for the
+// others.
+__device__ __forceinline__ uint32_t rec_str_operands(uint32_t op) {
+  return op == uint32_t(kOpName) ? 1u : (op == uint32_t(kOpEntryPoint) ? 2u : 0u);
+}
+
+// Operand words and string bytes of a record.  A string-bearing instruction
+// has its fixed operands and then the string, whose first NUL lies in its
+// last word (decode checked that), so its length is 4 * (string words - 1)
+// plus the bytes of the last word before the NUL.
 __device__ __forceinline__ void rec_counts(const RParams& P, const RecInst& ri, uint32_t& n_opnd, uint32_t& n_chars) {
   const uint32_t wc = ri.w0 >> 16, op = ri.w0 & 0xFFFFu;
-  if (op == uint32_t(kOpName)) {
+  const uint32_t k0 = rec_str_operands(op);
+  if (k0) {
     const uint32_t last = P.words[ri.pos + wc - 1];
     uint32_t k = 0;
     while (k < 4 && ((last >> (8 * k)) & 0xFFu) != 0) ++k;
-    n_opnd = 1;
-    n_chars = 4 * (wc - 3) + k;
+    n_opnd = k0;
+    n_chars = 4 * (wc - 2 - k0) + k;
   } else {
     n_opnd = wc - 1;
     n_chars = 0;
@@ -284,11 +292,12 @@ __global__ __launch_bounds__(kRecThreads) void k_rec_scatter(RParams P) {
       const RecInst ri = rec_inst(P, r);
       const uint32_t wc = ri.w0 >> 16, op = ri.w0 & 0xFFFFu;
       P.op[r] = uint16_t(op);
-      if (op == uint32_t(kOpName)) {
-        P.opnd[oo] = P.words[ri.pos + 1];
+      const uint32_t k0 = rec_str_operands(op);
+      if (k0) {
+        for (uint32_t i = 0; i < k0; ++i) P.opnd[oo + i] = P.words[ri.pos + 1 + i];
         const uint32_t nc = uint32_t(x & 0xFFFFFFFFull);
         for (uint32_t c = 0; c < nc; c += 4) {
-          const uint32_t w = P.words[ri.pos + 2 + c / 4];
+          const uint32_t w = P.words[ri.pos + 1 + k0 + c / 4];
 #pragma unroll
           for (uint32_t q = 0; q < 4; ++q)
             if (c + q < nc) P.chars[so + c + q] = uint8_t(w >> (8 * q));

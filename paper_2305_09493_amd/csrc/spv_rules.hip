@@ -1,9 +1,7 @@
 // Module-level rules (section "Validation Rules"): a module that passed every
 // structural and ID check must declare a capability (OpCapability, 17),
-// define its memory model (OpMemoryModel, 14) and declare a function
-// (OpFunction, 54).  The section's fourth rule, an entry point, needs
-// OpEntryPoint (15), outside the twelve-opcode grammar, so a module that
-// holds one has already failed the parse stage; that rule is not checked.
+// define its memory model (OpMemoryModel, 14), declare a function
+// (OpFunction, 54) and declare an entry point (OpEntryPoint, 15).
 //
 // The rules read the instruction index that the validate call wrote: module
 // m's opcodes are idx_op[mod_off[m] .. mod_off[m] + n_inst).  Two kernels on
@@ -15,12 +13,12 @@
 //                  chunk is walked by its lanes, 64 entries each, across
 //                  module boundaries (modules found by binary search over
 //                  mod_off).  The rule opcodes seen are ORed into presence
-//                  bits (sem_mask bits 8..10 of passing modules, whose
+//                  bits (sem_mask bits 8..11 of passing modules, whose
 //                  sem_mask is otherwise 0) with device atomics; a flush
 //                  that a plain read shows adds no new bit is skipped.
 //   k_rules_fin  : per module, presence bits -> SPV_E_MODULE_RULES with the
 //                  missing rules as 8 (capability) | 16 (memory model) |
-//                  32 (function).
+//                  32 (function) | 64 (entry point).
 // Bytes per index entry: 2 (opcode), plus 16 per module for the results.
 #include <hip/hip_runtime.h>
 
@@ -34,7 +32,7 @@ constexpr int64_t kRulesWave = 64 * kRulesPer;   // entries per wave chunk
 constexpr uint32_t kPresentShift = 8;
 
 __device__ __forceinline__ uint32_t rule_bit(uint32_t op) {
-  return op == 17u ? 1u : (op == 14u ? 2u : (op == 54u ? 4u : 0u));
+  return op == 17u ? 1u : (op == 14u ? 2u : (op == 54u ? 4u : (op == 15u ? 8u : 0u)));
 }
 
 // ORs presence bits into module m's sem_mask, unless a plain (cached) read
@@ -165,8 +163,9 @@ __global__ __launch_bounds__(kRulesBlock) void k_rules_scan(const uint16_t* idx_
 __global__ __launch_bounds__(kRulesBlock) void k_rules_fin(spv_result* results, int64_t M) {
   for (int64_t m = int64_t(blockIdx.x) * kRulesBlock + threadIdx.x; m < M; m += int64_t(gridDim.x) * kRulesBlock) {
     if (results[m].code != SPV_OK) continue;
-    const uint32_t present = (results[m].sem_mask >> kPresentShift) & 7u;
-    const uint32_t missing = ((present & 1u) ? 0u : 8u) | ((present & 2u) ? 0u : 16u) | ((present & 4u) ? 0u : 32u);
+    const uint32_t present = (results[m].sem_mask >> kPresentShift) & 15u;
+    const uint32_t missing = ((present & 1u) ? 0u : 8u) | ((present & 2u) ? 0u : 16u) | ((present & 4u) ? 0u : 32u) |
+                             ((present & 8u) ? 0u : 64u);
     results[m].sem_mask = missing;
     if (missing) results[m].code = SPV_E_MODULE_RULES;
   }

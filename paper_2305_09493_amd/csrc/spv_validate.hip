@@ -55,9 +55,11 @@ struct GEnt {
   uint8_t def;
   uint8_t use;
 };
-__device__ __constant__ GEnt kGrammar[12] = {
+constexpr int kNumOps = 13;
+__device__ __constant__ GEnt kGrammar[kNumOps] = {
     {5, 3, 65533, 0x0, 0x1},   // OpName          U S...
     {14, 3, 1, 0x0, 0x0},      // OpMemoryModel   L L
+    {15, 4, 65532, 0x0, 0x2},  // OpEntryPoint    L U S...
     {17, 2, 1, 0x0, 0x0},      // OpCapability    L
     {21, 4, 1, 0x1, 0x0},      // OpTypeInt       D L L
     {43, 4, 1, 0x2, 0x1},      // OpConstant      U D L
@@ -72,15 +74,19 @@ __device__ __constant__ GEnt kGrammar[12] = {
 
 // LDS grammar entry of an opcode (0 = unknown): bits 0..6 smallest word
 // count, bit 7 string operand, bits 8..23 count of accepted word counts,
-// bits 24..27 result-ID slots, bits 28..31 ID-use slots.
+// bits 24..27 result-ID slots, bits 28..31 ID-use slots.  The instructions
+// with a string (OpName, OpEntryPoint) have a variable word count whose
+// smallest value is their fixed operands, one string word and the first
+// word, so their string starts at operand slot lo - 1.
 constexpr uint32_t kEntStr = 0x80u;
+__device__ __forceinline__ uint32_t str_slot(uint32_t e) { return (e & 0x7Fu) - 1u; }
 
 __device__ __forceinline__ void init_table(uint32_t* tbl) {
   for (int i = threadIdx.x; i < 257; i += blockDim.x) tbl[i] = 0;
   __syncthreads();
-  if (threadIdx.x < 12) {
+  if (threadIdx.x < kNumOps) {
     GEnt g = kGrammar[threadIdx.x];
-    tbl[g.op] = uint32_t(g.lo) | (g.op == kOpName ? kEntStr : 0u) | (uint32_t(g.nok) << 8) | (uint32_t(g.def) << 24) |
+    tbl[g.op] = uint32_t(g.lo) | (g.nok > 1 ? kEntStr : 0u) | (uint32_t(g.nok) << 8) | (uint32_t(g.def) << 24) |
                 (uint32_t(g.use) << 28);
   }
   __syncthreads();
@@ -127,7 +133,7 @@ __device__ __forceinline__ uint32_t start_code(const uint32_t* words, const uint
   uint32_t e = tbl_lookup(tbl, op);
   if (((e >> 8) & 0xFFFFu) == 0) return SPV_E_UNKNOWN_OPCODE;
   if (!tbl_plausible(e, wc)) return SPV_E_BAD_WORD_COUNT;
-  if (op == kOpName && !string_ok_global(words + pos + 2, wc - 2)) return SPV_E_BAD_STRING;
+  if ((e & kEntStr) && !string_ok_global(words + pos + str_slot(e), wc - str_slot(e))) return SPV_E_BAD_STRING;
   return 0;
 }
 
@@ -196,8 +202,8 @@ struct Shared {
   static constexpr int kWinW = kWinWords;
   unsigned long long win[kWinWords];  // result-ID window bitmap of module jw
   uint32_t wmin[1];
-  uint32_t nname;              // OpName starts compacted into stage[] for the string checks
-  uint32_t badb[kTileWords / 32];  // tile positions whose OpName string is malformed
+  uint32_t nname;              // string-bearing starts compacted into stage[] for the string checks
+  uint32_t badb[kTileWords / 32];  // tile positions whose string is malformed
   LEnt cache;                  // module containing the previous tile's start
   int cache_ok;
 };
@@ -424,7 +430,7 @@ struct Lane {
   uint32_t rstbits;  // first-instruction positions of modules starting in [0, 16)
   uint32_t plmask;   // plausible instruction starts
   uint32_t farmask;  // plausible starts with word count >= 15
-  uint32_t namemask; // OpName candidate starts
+  uint32_t namemask; // candidate starts of string-bearing instructions (OpName, OpEntryPoint)
   uint32_t rolep[kLaneWords / 4];  // role bits per position (8 bits: result slots | use slots << 4)
   uint64_t F;        // transfer function
   uint32_t reach0;   // fast lanes: chain from the first candidate
@@ -489,11 +495,11 @@ __device__ __forceinline__ void lane_dp(const Shared& S, const VParams& P, Lane&
     }
     pl_m |= uint32_t(pl) << p;
     far_m |= uint32_t(pl && wc >= 15u) << p;
-    name_m |= uint32_t((L.w[p] & 0xFFFFu) == uint32_t(kOpName)) << p;
+    name_m |= ((e[p] >> 7) & 1u) << p;
     if ((p & 3) == 0) L.rolep[p >> 2] = 0;
     L.rolep[p >> 2] |= (e[p] >> 24) << (8 * (p & 3));
   }
-  // long instructions (only OpName can be one; rare): kept only when they
+  // long instructions (only string-bearing ones can be; rare): kept only when they
   // stay inside their module and the string words before the last hold no
   // NUL byte
   L.far_cand = false;
@@ -503,11 +509,12 @@ __device__ __forceinline__ void lane_dp(const Shared& S, const VParams& P, Lane&
       const int p = __builtin_ctz(fm);
       fm &= fm - 1;
       const int64_t pos = L.a + p;
-      const uint32_t wc = P.words[pos] >> 16;
+      const uint32_t w0 = P.words[pos];
+      const uint32_t wc = w0 >> 16;
       const int jm = kBounds ? lane_mod_at(L, p) : L.j0;
       bool ok = pos + int64_t(wc) <= S.list[jm].end;
       const uint32_t lim = wc - 1 < 18u ? wc - 1 : 18u;
-      for (uint32_t k = 2; ok && k < lim; ++k) {
+      for (uint32_t k = str_slot(tbl_lookup(S.tbl, w0 & 0xFFFFu)); ok && k < lim; ++k) {
         uint32_t x = P.words[pos + k];
         ok = ((x - 0x01010101u) & ~x & 0x80808080u) == 0;
       }
@@ -636,11 +643,12 @@ __device__ __forceinline__ void lane_scan(const SH& S, const VParams& P, Lane& L
       const int p = __builtin_ctz(fm);
       fm &= fm - 1;
       const int64_t pos = L.a + p;
-      const uint32_t wc = P.words[pos] >> 16;
+      const uint32_t w0 = P.words[pos];
+      const uint32_t wc = w0 >> 16;
       const int jm = kBounds ? lane_mod_at(L, p) : L.j0;
       bool ok = pos + int64_t(wc) <= S.list[jm].end;
       const uint32_t lim = wc - 1 < 18u ? wc - 1 : 18u;
-      for (uint32_t k = 2; ok && k < lim; ++k) {
+      for (uint32_t k = str_slot(tbl_lookup(S.tbl, w0 & 0xFFFFu)); ok && k < lim; ++k) {
         uint32_t x = P.words[pos + k];
         ok = ((x - 0x01010101u) & ~x & 0x80808080u) == 0;
       }
@@ -1083,7 +1091,9 @@ __global__ __launch_bounds__(kBlock, 6) void k_chain(VParams P) {
       // entry either joins it or is not a plausible start); starts after a
       // module start do not depend on the entry
       if (!L.slow) {
-        mask0 = L.reach0 & L.plmask & 0xFFFFu;
+        // plausible chain nodes (bits 0..15) and the node where the chain
+        // meets an invalid start (bits 16..31; the chain stops there)
+        mask0 = (L.reach0 & L.plmask & 0xFFFFu) | ((L.reach0 & ~L.plmask & 0xFFFFu) << 16);
         starts = 0;
         errs = 0;
       } else if (L.hdr && L.farmask == 0) {
@@ -1097,7 +1107,7 @@ __global__ __launch_bounds__(kBlock, 6) void k_chain(VParams P) {
           reach |= go << ((p + (L.w[p] >> 16)) & 31u);
         }
         ok0 = (cand & ~reach) == 0;
-        mask0 = reach & L.plmask & hm;
+        mask0 = (reach & L.plmask & hm) | ((reach & ~L.plmask & hm) << 16);
         const uint32_t fr = lane_forward(L, 99u);
         starts = fr & L.plmask & ~L.farmask & ~L.hdr & 0xFFFFu;
         errs = fr & ~L.plmask & ~L.hdr & 0xFFFFu;
@@ -1187,7 +1197,7 @@ __global__ __launch_bounds__(kResolveBlock) void k_resolve(VParams P) {
     else if (E >= kFar) bad = true;
   }
   if (real && (v.x & kSumFallback)) bad = true;
-  const uint32_t c0 = (E < 14u && ((v.y >> E) & 1u)) ? uint32_t(__popc(v.y >> E)) : 0u;
+  const uint32_t c0 = (E < 14u && ((v.y >> E) & 1u)) ? uint32_t(__popc((v.y & 0xFFFFu) >> E)) : 0u;
   const bool rs = real && (v.x & kSumReset);
   const uint32_t val = real ? (rs ? v.w : v.z + c0) : 0u;
   // inclusive segmented scan (bit 31: a module starts in the range)
@@ -1401,7 +1411,12 @@ __device__ __forceinline__ void main_body(SH& S, const VParams& P) {
         const uint32_t m0 = pr ? pr_m0 : P.tsum[4 * t + 1];
         const uint32_t h0 = L.hdr ? uint32_t(__builtin_ctz(L.hdr)) : 16u;
         if (Et < 14u && Et < h0) {
-          if ((m0 >> Et) & 1u) starts |= m0 & (~0u << Et);
+          if ((m0 >> Et) & 1u) {
+            // the entry is on the first lane's candidate chain: its starts
+            // and its error node from the entry on
+            starts |= m0 & 0xFFFFu & (~0u << Et);
+            errs |= (m0 >> 16) & (~0u << Et);
+          }
           else errs |= 1u << Et;
         }
       }
@@ -1505,7 +1520,7 @@ __device__ __forceinline__ void main_body(SH& S, const VParams& P) {
         break;
       }
     }
-    // OpName starts are compacted for the string checks
+    // starts of string-bearing instructions are compacted for the string checks
     if constexpr (!kRes) {
       uint32_t ns = starts & L.namemask;
       if (ns) {
@@ -1621,17 +1636,18 @@ __device__ __forceinline__ void main_body(SH& S, const VParams& P) {
     // is the start at p in list entry 0 (ranks continue the tile prefix)?
     auto in_first = [&](int p) -> bool { return lane_in_first && (rst & ((2u << p) - 1u)) == 0; };
 
-    // ---- OpName strings: one lane per compacted start, on the LDS copy of
+    // ---- strings (OpName, OpEntryPoint): one lane per compacted start, on the LDS copy of
     // the words; malformed ones are marked in badb and reported with the
     // parse errors
-    // one OpName start at tile position q: its string, on the LDS copy of the
+    // one string-bearing start at tile position q: its string, on the LDS copy of the
     // words; malformed ones are marked in badb and reported with the parse
     // errors
     auto check_name = [&](const int q) {
-      const uint32_t nw = (S.tw[q] >> 16) - 2;  // string words: 1..12 on this path
+      const uint32_t ss = str_slot(tbl_lookup(S.tbl, S.tw[q] & 0xFFFFu));
+      const uint32_t nw = (S.tw[q] >> 16) - ss;  // string words: 1..12 on this path
       uint32_t x[12];
 #pragma unroll
-      for (int k = 0; k < 12; ++k) x[k] = (uint32_t(k) < nw) ? S.tw[q + 2 + k] : 0u;
+      for (int k = 0; k < 12; ++k) x[k] = (uint32_t(k) < nw) ? S.tw[q + ss + k] : 0u;
       bool ok = true;
       uint32_t last = 0;
 #pragma unroll
@@ -1664,7 +1680,7 @@ __device__ __forceinline__ void main_body(SH& S, const VParams& P) {
 
     uint32_t own_names = 0;
     // resolved walk: one pass over the lane's starts for the grammar entry,
-    // the ID slots, the OpName marks and the instruction index (the tile
+    // the ID slots, the string marks and the instruction index (the tile
     // prefix is already known)
     if constexpr (kRes) {
       uint32_t name_m = 0;
@@ -1980,7 +1996,7 @@ __device__ __forceinline__ void main_body(SH& S, const VParams& P) {
     }
 
     // ---- parse errors: chain nodes that are not valid instructions, and
-    // OpName starts whose string is malformed
+    // string-bearing starts whose string is malformed
     {
       const uint32_t bad_names = (S.badb[lrel >> 5] >> (lrel & 31)) & 0xFFFFu;
       uint32_t ee = errs | bad_names;

@@ -40,7 +40,7 @@ def _check(r, label, **kw):
 
 
 def test_encode_generated_modules_and_round_trip():
-    mods = [spvgen.gen_module([20, i], n) for i, n in enumerate([3, 50, 1000, 4000, 20000, 7])]
+    mods = [spvgen.gen_module([20, i], n) for i, n in enumerate([5, 50, 1000, 4000, 20000, 7])]
     r = spvgen.pack_records(mods)
     gw, gmo = _check(r, "generated")
     b = spvgen.pack(mods)
@@ -59,7 +59,7 @@ def test_encode_block_sizes():
 
 def test_encode_failures_compacted():
     rng = np.random.default_rng(3)
-    mods = [spvgen.gen_module([22, i], int(rng.integers(3, 800))) for i in range(120)]
+    mods = [spvgen.gen_module([22, i], int(rng.integers(5, 800))) for i in range(120)]
     r = spvgen.pack_records(mods)
     op = r["op"].copy()
     opnd = r["opnd"].copy()
@@ -132,6 +132,8 @@ def test_encode_runs_beyond_lds_staging():
     mods[0][400] = (5, [1], b"a" * 1500)
     mods[0][401] = (5, [1], b"b" * 1501)
     mods[1][200] = (62, list(range(1, 2001)), b"")   # operand count error, 2000 operands
+    mods[1][300] = (15, [6, 1], b"e" * 2001)          # an entry point with a 501-word name
+    mods[0][500] = (15, [6, 1], b"main")
     mods[2][300] = (5, [1], b"x" * 270000)           # 1 + 1 + 67501 words: too long
     tiny = [_plain_module(rng, 3) for _ in range(700)]
     tiny[10] = []                                     # empty modules among tiny ones

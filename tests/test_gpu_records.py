@@ -39,7 +39,7 @@ def _check(words, mod_off, label, semantic=False):
 
 
 def test_records_of_generated_and_faulted_modules():
-    mods = [spvgen.gen_module([30, i], n) for i, n in enumerate([3, 40, 1000, 5000, 17, 20000])]
+    mods = [spvgen.gen_module([30, i], n) for i, n in enumerate([5, 40, 1000, 5000, 17, 20000])]
     b = spvgen.pack(mods)
     _check(b.words, b.mod_off, "generated")
     _check(b.words, b.mod_off, "generated, from validate", semantic=True)

@@ -1,6 +1,6 @@
 """GPU parity of the module-level rules (spv_validate with
 SPV_OPT_MODULE_RULES) against the oracle's rules stage: mixed batches with
-modules lacking each rule (rewritten so that every ID check still passes),
+modules lacking each rule (capability, memory model, function, entry point) (rewritten so that every ID check still passes),
 modules failing earlier stages, header-only, short and empty modules, a
 multi-tile module without functions, the full lognormal batch, and graph
 replays of the captured call on changing inputs."""
@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import spvgen
-from spvgen import K_CAP, K_FUNC, K_MEM, K_TYPEINT
+from spvgen import K_CAP, K_ENTRY, K_FUNC, K_MEM, K_TYPEINT
 
 pytestmark = pytest.mark.gpu
 
@@ -54,6 +54,17 @@ def drop_functions(mod):
     return w
 
 
+def drop_entry_point(mod):
+    """The prologue's OpEntryPoint (5 words) becomes an OpName of its function
+    with a 9-character name (5 words too)."""
+    w = mod.words.copy()
+    for s in mod.starts[mod.kind == K_ENTRY]:
+        fn = int(w[s + 2])
+        name = b"mainmain\0\0\0\0"
+        w[s:s + 5] = [(5 << 16) | 5, fn] + [int.from_bytes(name[k:k + 4], "little") for k in (0, 4, 8)]
+    return w
+
+
 def _run(words_list, label):
     import torch
 
@@ -81,10 +92,14 @@ def _run(words_list, label):
 
 
 def test_rules_mixed_batch():
-    mods = [spvgen.gen_module([11, i], n) for i, n in enumerate([3, 4, 9, 40, 200, 3000, 60_000, 20_000, 700])]
+    mods = [spvgen.gen_module([11, i], n) for i, n in enumerate([5, 6, 9, 40, 200, 3000, 60_000, 20_000, 700])]
     words = [m.words for m in mods]
     words += [drop_capability(mods[5]), drop_memory_model(mods[4]), drop_functions(mods[6]),
-              drop_functions(mods[7]), drop_capability(mods[3])]
+              drop_functions(mods[7]), drop_capability(mods[3]), drop_entry_point(mods[0]),
+              drop_entry_point(mods[6]), drop_entry_point(mods[8])]
+    ne = spvgen.gen_module([11, 98], 4000)
+    ne.words = drop_entry_point(ne)
+    words.append(drop_functions(ne))
     both = spvgen.gen_module([11, 99], 5000)
     w = drop_memory_model(both)
     both.words = w
@@ -100,7 +115,7 @@ def test_rules_mixed_batch():
     codes = set(int(c) for c in o[:, 0])
     masks = set(int(s) for c, s in zip(o[:, 0], o[:, 1]) if c == oracle.E_MODULE_RULES)
     assert {0, 1, 9, oracle.E_MODULE_RULES} <= codes
-    assert {8, 16, 32, 56} <= masks
+    assert {8, 16, 32, 64, 96, 120} <= masks
 
 
 def test_rules_single_module_without_functions():
@@ -126,10 +141,10 @@ def test_rules_graph_replays():
 
     import paper_2305_09493_amd as spv
     base = [spvgen.gen_module([13, i], 2000) for i in range(12)]
-    variants = [lambda m: m.words, drop_capability, drop_memory_model, drop_functions]
+    variants = [lambda m: m.words, drop_capability, drop_memory_model, drop_functions, drop_entry_point]
 
     def batch(seed):
-        return [variants[(i + seed) % 4](m) for i, m in enumerate(base)]
+        return [variants[(i + seed) % 5](m) for i, m in enumerate(base)]
 
     w0 = batch(0)
     sizes = np.array([w.size for w in w0], np.int64)
@@ -168,4 +183,4 @@ def test_rules_graph_replays():
         # eager work between replays
         spv.validate(words, mod_off, out=(res, io, iop), workspace=ws)
         torch.cuda.synchronize()
-    assert {8, 16} <= seen
+    assert {8, 16, 32, 64} <= seen

@@ -14,7 +14,7 @@ def _pool():
     rng = np.random.default_rng(31)
     mods = []
     for i in range(160):
-        m = spvgen.gen_module([31, i], int(rng.integers(3, 6000)))
+        m = spvgen.gen_module([31, i], int(rng.integers(5, 6000)))
         if i % 9 == 3:
             m = spvgen.FAULTS[i % 3](m, rng)
         mods.append(m.words)

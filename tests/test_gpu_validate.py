@@ -51,7 +51,7 @@ def test_module_sizes_around_lane_and_tile_edges(n_words):
 
 def test_boundaries_at_every_lane_offset():
     rng = np.random.default_rng(5)
-    mods = [spvgen.gen_module([6, i], int(rng.integers(3, 40))) for i in range(600)]
+    mods = [spvgen.gen_module([6, i], int(rng.integers(5, 40))) for i in range(600)]
     b = spvgen.pack(mods)
     compare(b.words, b.mod_off, label="small modules, boundaries everywhere")
 
@@ -115,7 +115,7 @@ def test_random_mutations():
     rng = np.random.default_rng(13)
     mods = []
     for i in range(200):
-        m = spvgen.gen_module([10, i], int(rng.integers(3, 3000)))
+        m = spvgen.gen_module([10, i], int(rng.integers(5, 3000)))
         w = m.words.copy()
         for _ in range(int(rng.integers(0, 3))):
             p = int(rng.integers(0, w.size))
@@ -173,3 +173,38 @@ def test_real_modules_mixed_with_generated():
     compare(words, mod_off, semantic=False, label="real + generated, decode")
     for m in real:
         compare(m, [0, m.size], label=f"real module alone ({m.size} words)")
+
+
+def _name_words(wc):
+    """An OpName of %1 with wc words (its string: wc - 2 words, NUL in the last)."""
+    n = 4 * (wc - 2) - 1
+    b = (b"n" * n + b"\0").ljust(4 * (wc - 2), b"\0")
+    return [(wc << 16) | 5, 1] + [int.from_bytes(b[k:k + 4], "little") for k in range(0, len(b), 4)]
+
+
+@pytest.mark.parametrize("semantic", [True, False])
+def test_invalid_start_in_first_lane_after_tile_entry(semantic):
+    # The chain enters a tile at offset e (an OpName crossing the tile start
+    # ends there), walks one-word instructions, and meets an invalid
+    # instruction (OpLabel with word count 1) at offset q of the tile's first
+    # lane: the parse error must be found at q.
+    mods = []
+    for e in (0, 1, 2, 5, 11):
+        for q in range(e + 1, 16):
+            m = spvgen.gen_module([14, q, e], 400)
+            w = [int(x) for x in m.words[:int(m.starts[spvgen.N_PROLOGUE])]]
+            base = sum(x.size for x in mods)
+            if e == 0:
+                w += [0x000100FD] * ((-(base + len(w))) % T)
+            else:
+                w += [0x000100FD] * ((-3 - (base + len(w))) % T)
+                w += _name_words(3 + e)
+            assert (base + len(w)) % T == e
+            w += [0x000100FD] * (q - e)
+            w += [0x000100F8, 0x000000FF]
+            w += [int(x) for x in m.words[int(m.starts[spvgen.N_PROLOGUE]):]]
+            mods.append(np.array(w, np.uint32))
+    offs = np.concatenate([[0], np.cumsum([x.size for x in mods])]).astype(np.int64)
+    words = np.concatenate(mods)
+    res = compare(words, offs, semantic=semantic, label="invalid start in a tile's first lane")
+    assert np.all(res[:, 0] == 5)
