@@ -166,6 +166,24 @@ int spv_validate(spv_ctx *ctx, const uint32_t *words, const int64_t *mod_off, in
                  uint32_t *idx_off, uint16_t *idx_op, int64_t idx_cap, spv_result *results, uint32_t option_flags,
                  void *ws, size_t ws_bytes, void *stream);
 
+/* spv_validate for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same call without a workspace argument.  Its workspace is the
+ * library's own scratch array, SPV_NOALLOC_SCRATCH_BYTES per GPU, which each
+ * GPU the library runs on holds until the process ends; its address on a
+ * device is resolved by spv_create.  The call allocates nothing, creates no
+ * event (timing is not recorded on this path) and needs no initialised
+ * scratch.  Every call on one GPU shares that GPU's scratch, so calls that
+ * overlap on one GPU (different streams without ordering) race: order them.
+ * Arguments and results as for spv_validate; SPV_ERR_WORKSPACE when the
+ * batch needs more than the scratch holds (spv_workspace_size(...) >
+ * SPV_NOALLOC_SCRATCH_BYTES: about 7.5M words for one module), SPV_ERR_HIP
+ * when the scratch address could not be resolved on the context's device. */
+#define SPV_NOALLOC_SCRATCH_BYTES (64u << 20)
+int spv_validate_noalloc(spv_ctx *ctx, const uint32_t *words, const int64_t *mod_off, int64_t n_modules,
+                         int64_t n_words, uint32_t *idx_off, uint16_t *idx_op, int64_t idx_cap, spv_result *results,
+                         uint32_t option_flags, void *stream);
+
 /* Bytes of workspace spv_decode_records needs. */
 int spv_records_workspace_size(spv_ctx *ctx, int64_t n_modules, int64_t n_words, size_t *bytes);
 

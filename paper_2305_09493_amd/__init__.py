@@ -58,6 +58,7 @@ def load_library():
         lib.spv_workspace_size.argtypes = [P, I64, I64, ctypes.POINTER(SZ)]
         lib.spv_decode.argtypes = [P, P, P, I64, I64, P, P, I64, P, P, SZ, P]
         lib.spv_validate.argtypes = [P, P, P, I64, I64, P, P, I64, P, U32, P, SZ, P]
+        lib.spv_validate_noalloc.argtypes = [P, P, P, I64, I64, P, P, I64, P, U32, P]
         lib.spv_encode_bound.argtypes = [I64, I64, I64, I64, I64, ctypes.POINTER(I64)]
         lib.spv_encode_workspace_size.argtypes = [P, I64, I64, ctypes.POINTER(SZ)]
         lib.spv_encode.argtypes = [P, P, P, P, P, P, P, I64, I64, U32, U32, P, P, I64, P, P, P, SZ, P]
@@ -67,7 +68,7 @@ def load_library():
         lib.spv_get_tuning.argtypes = [P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
         lib.spv_read_timing.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)]
         for name in ("spv_create", "spv_destroy", "spv_set_tuning", "spv_workspace_size", "spv_decode",
-                     "spv_validate", "spv_encode_bound", "spv_encode_workspace_size", "spv_encode",
+                     "spv_validate", "spv_validate_noalloc", "spv_encode_bound", "spv_encode_workspace_size", "spv_encode",
                      "spv_set_timing", "spv_read_timing", "spv_get_tuning", "spv_server_create", "spv_server_start", "spv_server_submit",
            "spv_server_poll", "spv_server_stats", "spv_server_destroy", "spv_server_cancel"):
             getattr(lib, name).restype = ctypes.c_int
@@ -76,7 +77,7 @@ def load_library():
 
 
 EXPORTS = ("spv_create", "spv_destroy", "spv_last_hip_error", "spv_set_tuning", "spv_workspace_size",
-           "spv_decode", "spv_validate", "spv_encode_bound", "spv_encode_workspace_size", "spv_encode",
+           "spv_decode", "spv_validate", "spv_validate_noalloc", "spv_encode_bound", "spv_encode_workspace_size", "spv_encode",
            "spv_records_workspace_size", "spv_decode_records",
            "spv_set_timing", "spv_read_timing", "spv_get_tuning", "spv_server_create", "spv_server_start", "spv_server_submit",
            "spv_server_poll", "spv_server_stats", "spv_server_destroy", "spv_server_cancel")
@@ -228,6 +229,37 @@ def validate(words, mod_off, index: bool = True, ctx: Optional[Context] = None, 
         raise SpvError("module_rules needs the instruction index (index=True)")
     return _run(True, words, mod_off, index, ctx, stream, out, workspace,
                 OPT_MODULE_RULES if module_rules else 0)
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20  # SPV_NOALLOC_SCRATCH_BYTES
+
+
+def validate_noalloc(words, mod_off, out, ctx: Optional[Context] = None, stream=None, module_rules: bool = False):
+    """spv_validate_noalloc: validate into caller-given outputs (results
+    int32[M, 4], and idx_off int32[>= W] / idx_op int16[>= W] or None) with
+    the library's own scratch instead of a workspace; nothing is allocated.
+    Calls that overlap on one GPU race on its scratch."""
+    torch = _torch()
+    ctx = ctx or context(words.device.index)
+    W = int(words.numel())
+    M = int(mod_off.numel()) - 1
+    if not (words.is_cuda and mod_off.is_cuda and mod_off.dtype == torch.int64 and mod_off.is_contiguous()):
+        raise SpvError("words and mod_off must be CUDA tensors, mod_off contiguous int64")
+    if words.dtype not in (torch.int32, torch.uint32) or not words.is_contiguous():
+        raise SpvError("words must be a contiguous int32 / uint32 CUDA tensor")
+    results, idx_off, idx_op = out
+    if results.numel() < 4 * M or not results.is_contiguous():
+        raise SpvError(f"results must be a contiguous int32 CUDA tensor of {M} rows of 4")
+    index = idx_off is not None
+    if index != (idx_op is not None):
+        raise SpvError("give both idx_off and idx_op, or neither")
+    if module_rules and not index:
+        raise SpvError("module_rules needs the instruction index")
+    idx_cap = min(int(idx_off.numel()), int(idx_op.numel())) if index else 0
+    rc = ctx.lib.spv_validate_noalloc(ctx.h, _ptr(words), _ptr(mod_off), M, W, _ptr(idx_off), _ptr(idx_op), idx_cap,
+                                      _ptr(results), OPT_MODULE_RULES if module_rules else 0, _stream(stream))
+    ctx.check(rc, "spv_validate_noalloc")
+    return results, idx_off, idx_op
 
 
 def decode(words, mod_off, index: bool = True, ctx: Optional[Context] = None, stream=None, out=None,

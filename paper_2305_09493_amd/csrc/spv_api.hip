@@ -4,10 +4,16 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <utility>
 #include <vector>
 
 #include "spv_internal.h"
+
+// Scratch of spv_validate_noalloc: one copy per GPU, held until the process
+// ends.  Host code never uses this name as an address: the device address of
+// each GPU's copy is resolved once per device (spv_create) and kept below.
+static __device__ __align__(256) unsigned char scratch[SPV_NOALLOC_SCRATCH_BYTES];
 
 struct spv_ctx {
   int device;
@@ -24,6 +30,7 @@ struct spv_ctx {
   bool timing;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;  // created events
   size_t ev_used;                                          // pairs recorded since the last read
+  void* scratch;       // this device's copy of the no-allocation scratch (nullptr if unresolved)
 };
 
 namespace spv {
@@ -34,6 +41,26 @@ int encode_occupancy(int pass);
 }
 
 namespace {
+
+// Device address of each GPU's scratch copy, resolved once per device.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+
+// (with `dev` current)
+void* resolve_scratch(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch[dev] == nullptr) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    g_scratch[dev] = ptr;
+  }
+  return g_scratch[dev];
+}
 
 struct DeviceGuard {
   int prev = -1;
@@ -67,7 +94,7 @@ int check_launch(spv_ctx* ctx) {
 
 int run_validate(spv_ctx* ctx, const uint32_t* words, const int64_t* mod_off, int64_t n_modules, int64_t n_words,
                  uint32_t* idx_off, uint16_t* idx_op, int64_t idx_cap, spv_result* results, int semantic, void* ws,
-                 size_t ws_bytes, void* stream) {
+                 size_t ws_bytes, void* stream, bool allow_timing = true) {
   if (!ctx) return SPV_ERR_INVALID_ARG;
   if (n_modules < 0 || n_words < 0) return SPV_ERR_INVALID_ARG;
   if (n_modules >= (int64_t(1) << 31) - 1) return SPV_ERR_LIMIT;
@@ -121,7 +148,7 @@ int run_validate(spv_ctx* ctx, const uint32_t* words, const int64_t* mod_off, in
   if (grid > p.n_tiles) grid = p.n_tiles;
   if (grid > 0) {
     std::pair<hipEvent_t, hipEvent_t>* ev = nullptr;
-    if (ctx->timing) {
+    if (ctx->timing && allow_timing) {
       if (ctx->ev_used == ctx->ev_pool.size()) {
         std::pair<hipEvent_t, hipEvent_t> e;
         hipError_t he = hipEventCreate(&e.first);
@@ -205,6 +232,7 @@ int spv_create(spv_ctx** out, int hip_device) {
     int wocc = spv::walk_occupancy();
     c->walk_occ = wocc > 0 ? wocc : 2;
     c->blocks_per_cu = occ > 0 ? (occ < 8 ? occ : 8) : 2;
+    c->scratch = resolve_scratch(hip_device);
     int eo = spv::encode_occupancy(0);
     c->enc_count_occ = eo > 0 ? eo : 2;
     eo = spv::encode_occupancy(1);
@@ -292,6 +320,25 @@ int spv_validate(spv_ctx* ctx, const uint32_t* words, const int64_t* mod_off, in
   if (rules && n_words > 0 && !idx_op) return SPV_ERR_INVALID_ARG;
   const int rc = run_validate(ctx, words, mod_off, n_modules, n_words, idx_off, idx_op, idx_cap, results, 1, ws,
                               ws_bytes, stream);
+  if (rc != SPV_SUCCESS || !rules || n_modules == 0) return rc;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail_hip(ctx, hipErrorInvalidDevice);
+  spv::launch_rules(idx_op, mod_off, results, n_modules, n_words, static_cast<hipStream_t>(stream));
+  return check_launch(ctx);
+}
+
+int spv_validate_noalloc(spv_ctx* ctx, const uint32_t* words, const int64_t* mod_off, int64_t n_modules,
+                         int64_t n_words, uint32_t* idx_off, uint16_t* idx_op, int64_t idx_cap, spv_result* results,
+                         uint32_t option_flags, void* stream) {
+  if (!ctx || n_modules < 0 || n_words < 0) return SPV_ERR_INVALID_ARG;
+  if ((option_flags & ~SPV_OPT_MODULE_RULES) != 0) return SPV_ERR_INVALID_ARG;
+  if (spv::make_layout(n_modules, n_words).total > size_t(SPV_NOALLOC_SCRATCH_BYTES)) return SPV_ERR_WORKSPACE;
+  if (ctx->scratch == nullptr) return fail_hip(ctx, hipErrorInvalidSymbol);
+  const bool rules = (option_flags & SPV_OPT_MODULE_RULES) != 0;
+  if (rules && n_words > 0 && !idx_op) return SPV_ERR_INVALID_ARG;
+  // no event recording on this path (nothing is created or allocated)
+  const int rc = run_validate(ctx, words, mod_off, n_modules, n_words, idx_off, idx_op, idx_cap, results, 1,
+                              ctx->scratch, size_t(SPV_NOALLOC_SCRATCH_BYTES), stream, false);
   if (rc != SPV_SUCCESS || !rules || n_modules == 0) return rc;
   DeviceGuard g(ctx->device);
   if (!g.ok) return fail_hip(ctx, hipErrorInvalidDevice);
