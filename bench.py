@@ -177,9 +177,9 @@ def records_leg(ctx, words, mod_off, idx_off, res, W, steps=10):
 
 def rules_leg(ctx, words, mod_off, plain_ms, steps=10):
     """The validate call with the module-level rules (a capability, the
-    memory model, a function) as a last stage, on the timed module: graph
-    replays of the captured call, and the time the rules add to the plain
-    call's step."""
+    memory model, a function, an entry point) as a last stage, on the timed
+    module: graph replays of the captured call, and the time the rules add to
+    the plain call's step."""
     import torch
 
     import paper_2305_09493_amd as spv

@@ -160,8 +160,7 @@ int spv_decode(spv_ctx *ctx, const uint32_t *words, const int64_t *mod_off, int6
 /* Validate: decode plus the semantic stage (bound, define-once, undefined
  * IDs).  Same arguments as spv_decode, plus option_flags: 0, or
  * SPV_OPT_MODULE_RULES to add the module-level rules of section "Validation
- * Rules" as a last stage (SPV_ERR_INVALID_ARG for other bits, or for the
- * rules without idx_op when n_words > 0). */
+ * Rules" as a last stage (SPV_ERR_INVALID_ARG for other bits). */
 int spv_validate(spv_ctx *ctx, const uint32_t *words, const int64_t *mod_off, int64_t n_modules, int64_t n_words,
                  uint32_t *idx_off, uint16_t *idx_op, int64_t idx_cap, spv_result *results, uint32_t option_flags,
                  void *ws, size_t ws_bytes, void *stream);

@@ -224,9 +224,7 @@ def validate(words, mod_off, index: bool = True, ctx: Optional[Context] = None, 
     """Per-module results int32[M, 4] (code, sem_mask, err_word, n_inst) and,
     if index, the gapped-CSR instruction index (idx_off int32[W], idx_op
     int16[W]).  module_rules adds the module-level rules as a last stage
-    (E_MODULE_RULES; needs the index)."""
-    if module_rules and not index:
-        raise SpvError("module_rules needs the instruction index (index=True)")
+    (E_MODULE_RULES)."""
     return _run(True, words, mod_off, index, ctx, stream, out, workspace,
                 OPT_MODULE_RULES if module_rules else 0)
 
@@ -253,8 +251,6 @@ def validate_noalloc(words, mod_off, out, ctx: Optional[Context] = None, stream=
     index = idx_off is not None
     if index != (idx_op is not None):
         raise SpvError("give both idx_off and idx_op, or neither")
-    if module_rules and not index:
-        raise SpvError("module_rules needs the instruction index")
     idx_cap = min(int(idx_off.numel()), int(idx_op.numel())) if index else 0
     rc = ctx.lib.spv_validate_noalloc(ctx.h, _ptr(words), _ptr(mod_off), M, W, _ptr(idx_off), _ptr(idx_op), idx_cap,
                                       _ptr(results), OPT_MODULE_RULES if module_rules else 0, _stream(stream))

@@ -94,7 +94,7 @@ int check_launch(spv_ctx* ctx) {
 
 int run_validate(spv_ctx* ctx, const uint32_t* words, const int64_t* mod_off, int64_t n_modules, int64_t n_words,
                  uint32_t* idx_off, uint16_t* idx_op, int64_t idx_cap, spv_result* results, int semantic, void* ws,
-                 size_t ws_bytes, void* stream, bool allow_timing = true) {
+                 size_t ws_bytes, void* stream, bool allow_timing = true, bool rules = false) {
   if (!ctx) return SPV_ERR_INVALID_ARG;
   if (n_modules < 0 || n_words < 0) return SPV_ERR_INVALID_ARG;
   if (n_modules >= (int64_t(1) << 31) - 1) return SPV_ERR_LIMIT;
@@ -134,6 +134,7 @@ int run_validate(spv_ctx* ctx, const uint32_t* words, const int64_t* mod_off, in
   p.sched_static = 0;
   // small batches: the second pass decides its own work (no phase-1 launch)
   p.p1_inline = (semantic && n_modules <= 256 && p.n_tiles > 0) ? 1 : 0;
+  p.rules = rules ? 1 : 0;
   hipStream_t s = static_cast<hipStream_t>(stream);
 
   int64_t plan_units = n_modules > p.n_tiles ? n_modules : p.n_tiles;
@@ -174,18 +175,11 @@ int run_validate(spv_ctx* ctx, const uint32_t* words, const int64_t* mod_off, in
     if (wgrid > p.n_tiles) wgrid = p.n_tiles;
     spv::launch_walk(p, int(wgrid), s);
     if ((r = check_launch(ctx))) return r;
-    // Static tile order needs every block resident at once: a cooperative
-    // launch guarantees that.  Stream capture keeps the claimed order.
-    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    hipError_t he = hipStreamIsCapturing(s, &cs);
-    if (he != hipSuccess) return fail_hip(ctx, he);
-    p.sched_static = (cs == hipStreamCaptureStatusNone && ctx->blocks_per_cu <= ctx->occupancy) ? 1 : 0;
-    he = spv::launch_main(p, int(grid), s);
-    if (he != hipSuccess && p.sched_static) {
-      (void)hipGetLastError();
-      p.sched_static = 0;
-      he = spv::launch_main(p, int(grid), s);
-    }
+    // the single-pass walk (returns at once when the resolved walk ran):
+    // tiles are claimed in order from a counter, so a tile's predecessors
+    // are always held by running blocks, whatever the residency
+    p.sched_static = 0;
+    hipError_t he = spv::launch_main(p, int(grid), s);
     if (he != hipSuccess) return fail_hip(ctx, he);
     if ((r = check_launch(ctx))) return r;
     if (ev) {
@@ -317,14 +311,8 @@ int spv_validate(spv_ctx* ctx, const uint32_t* words, const int64_t* mod_off, in
                  void* ws, size_t ws_bytes, void* stream) {
   if ((option_flags & ~SPV_OPT_MODULE_RULES) != 0) return SPV_ERR_INVALID_ARG;
   const bool rules = (option_flags & SPV_OPT_MODULE_RULES) != 0;
-  if (rules && n_words > 0 && !idx_op) return SPV_ERR_INVALID_ARG;
-  const int rc = run_validate(ctx, words, mod_off, n_modules, n_words, idx_off, idx_op, idx_cap, results, 1, ws,
-                              ws_bytes, stream);
-  if (rc != SPV_SUCCESS || !rules || n_modules == 0) return rc;
-  DeviceGuard g(ctx->device);
-  if (!g.ok) return fail_hip(ctx, hipErrorInvalidDevice);
-  spv::launch_rules(idx_op, mod_off, results, n_modules, n_words, static_cast<hipStream_t>(stream));
-  return check_launch(ctx);
+  return run_validate(ctx, words, mod_off, n_modules, n_words, idx_off, idx_op, idx_cap, results, 1, ws, ws_bytes,
+                      stream, true, rules);
 }
 
 int spv_validate_noalloc(spv_ctx* ctx, const uint32_t* words, const int64_t* mod_off, int64_t n_modules,
@@ -335,15 +323,9 @@ int spv_validate_noalloc(spv_ctx* ctx, const uint32_t* words, const int64_t* mod
   if (spv::make_layout(n_modules, n_words).total > size_t(SPV_NOALLOC_SCRATCH_BYTES)) return SPV_ERR_WORKSPACE;
   if (ctx->scratch == nullptr) return fail_hip(ctx, hipErrorInvalidSymbol);
   const bool rules = (option_flags & SPV_OPT_MODULE_RULES) != 0;
-  if (rules && n_words > 0 && !idx_op) return SPV_ERR_INVALID_ARG;
   // no event recording on this path (nothing is created or allocated)
-  const int rc = run_validate(ctx, words, mod_off, n_modules, n_words, idx_off, idx_op, idx_cap, results, 1,
-                              ctx->scratch, size_t(SPV_NOALLOC_SCRATCH_BYTES), stream, false);
-  if (rc != SPV_SUCCESS || !rules || n_modules == 0) return rc;
-  DeviceGuard g(ctx->device);
-  if (!g.ok) return fail_hip(ctx, hipErrorInvalidDevice);
-  spv::launch_rules(idx_op, mod_off, results, n_modules, n_words, static_cast<hipStream_t>(stream));
-  return check_launch(ctx);
+  return run_validate(ctx, words, mod_off, n_modules, n_words, idx_off, idx_op, idx_cap, results, 1, ctx->scratch,
+                      size_t(SPV_NOALLOC_SCRATCH_BYTES), stream, false, rules);
 }
 
 int spv_encode_bound(int64_t n_modules, int64_t n_records, int64_t n_opnd_words, int64_t n_string_records,

@@ -58,10 +58,15 @@ enum : uint32_t {
   kModHdrOk = 32u,
 };
 
+// Module-level rule presence bits (section "Validation Rules") in
+// ModState::flags: 1 capability, 2 memory model, 4 function, 8 entry point,
+// shifted by kModRuleShift.
+constexpr uint32_t kModRuleShift = 8;
+
 struct ModState {
   unsigned long long err_key;   // (offset << 8) | code of the first failing instruction (atomicMin)
   unsigned long long err_rank;  // (offset << 32) | instructions before it (atomicMin)
-  uint32_t flags;               // kMod* bits (atomicOr)
+  uint32_t flags;               // kMod* bits and rule presence bits (atomicOr)
   uint32_t def_count;           // distinct in-bound result IDs (atomicAdd)
   uint32_t n_total;             // instructions of a module whose parse did not fail
   uint32_t bound;               // header word 3
@@ -170,6 +175,7 @@ struct VParams {
   // order from a counter
   int sched_static;
   int p1_inline;  // k_pass2 computes finalize phase 1 itself (at most 256 modules; no k_finalize(1) launch)
+  int rules;      // finalize applies the module-level rules
 };
 
 // Grammar entry for opcode < 256 (index 256 = any other opcode):
@@ -299,8 +305,5 @@ inline RLayout make_rlayout(int64_t n_modules, int64_t n_words) {
 }
 
 void launch_records(const RParams& p, hipStream_t s);
-// module-level rules over the index of a finished validate call
-void launch_rules(const uint16_t* idx_op, const int64_t* mod_off, spv_result* results, int64_t M, int64_t W,
-                  hipStream_t s);
 
 }  // namespace spv

@@ -184,3 +184,25 @@ def test_rules_graph_replays():
         spv.validate(words, mod_off, out=(res, io, iop), workspace=ws)
         torch.cuda.synchronize()
     assert {8, 16, 32, 64} <= seen
+
+
+def test_rules_without_the_index():
+    """The rules come from the walk itself: the call without the index gives
+    the same results."""
+    import torch
+
+    import paper_2305_09493_amd as spv
+    from gpu_util import to_dev
+    mods = [spvgen.gen_module([14, i], n) for i, n in enumerate([5, 300, 4000, 9000])]
+    words = [m.words for m in mods] + [drop_capability(mods[1]), drop_entry_point(mods[2]),
+                                       drop_functions(mods[3]), drop_memory_model(mods[0])]
+    sizes = np.array([w.size for w in words], np.int64)
+    mod_off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    flat = np.concatenate(words).astype(np.uint32)
+    w, mo = to_dev(flat, mod_off)
+    res, _, _ = spv.validate(w, mo, index=False, module_rules=True)
+    torch.cuda.synchronize()
+    o = oracle.validate(flat, mod_off, semantic=True, index=False, rules=True)
+    want = np.stack([o[k] for k in ("code", "sem_mask", "err_word", "n_inst")], axis=1).astype(np.uint32)
+    assert np.array_equal(res.cpu().numpy().view(np.uint32), want)
+    assert {8, 16, 32, 64} <= set(int(x) for x in want[:, 1])
