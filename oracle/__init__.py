@@ -23,6 +23,8 @@ OK, E_TRUNCATED_HEADER, E_BAD_MAGIC, E_BAD_VERSION, E_BAD_SCHEMA = 0, 1, 2, 3, 4
 E_BAD_WORD_COUNT, E_UNKNOWN_OPCODE, E_BAD_STRING = 5, 6, 7
 E_ID_OUT_OF_BOUND, E_DUPLICATE_ID, E_UNDEFINED_ID = 8, 9, 10
 E_MODULE_RULES = 11  # with rules: sem_mask = 8 no OpCapability | 16 no OpMemoryModel | 32 no OpFunction | 64 no OpEntryPoint
+# disassembly options, the options listing's five switches in its order
+DIS_HIGHLIGHT, DIS_INLINE_NAMES, DIS_NO_INDENT, DIS_GROUP, DIS_NO_HEADER = 1, 2, 4, 8, 16
 ENC_OK, ENC_UNKNOWN_OPCODE, ENC_OPERAND_COUNT, ENC_BAD_STRING, ENC_TOO_LONG, ENC_BAD_ID = range(6)
 
 RESULT_DTYPE = np.dtype([("code", "<u4"), ("sem_mask", "<u4"), ("err_word", "<u4"), ("n_inst", "<u4")])
@@ -53,6 +55,8 @@ def _load():
             lib.oracle_encode.argtypes = [P, P, P, P, P, P, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint32, P, P,
                                           ctypes.c_int64, P, P]
             lib.oracle_encode.restype = ctypes.c_int64
+            lib.oracle_disassemble.argtypes = [P, P, ctypes.c_int64, ctypes.c_uint32, P, ctypes.c_int64, P]
+            lib.oracle_disassemble.restype = ctypes.c_int64
             _lib = lib
     return _lib
 
@@ -136,3 +140,25 @@ def encode(op, opnd_off, opnd, str_off, chars, rec_mod_off, version_word: int = 
     if n < 0:
         raise RuntimeError("oracle_encode: output capacity exceeded")
     return out[:n].copy(), word_mod_off, code, bad
+
+
+def disassemble(words, mod_off, options: int = 0, text_cap=None):
+    """(text bytes, text_mod_off int64[M+1], total) for a batch: module m's text
+    is text[text_mod_off[m] : text_mod_off[m+1]].  With text_cap, only the
+    first min(total, text_cap) bytes are produced (total is always the full
+    size)."""
+    lib = _load()
+    words = _contig(words, np.uint32)
+    mod_off = _contig(mod_off, np.int64)
+    m = mod_off.size - 1
+    tmo = np.zeros(m + 1, np.int64)
+    if text_cap is None:
+        total = lib.oracle_disassemble(_ptr(words), _ptr(mod_off), m, options, None, 0, _ptr(tmo))
+        if total < 0:
+            raise RuntimeError("oracle_disassemble failed")
+        text_cap = total
+    buf = np.zeros(max(int(text_cap), 1), np.uint8)
+    total = lib.oracle_disassemble(_ptr(words), _ptr(mod_off), m, options, _ptr(buf), int(text_cap), _ptr(tmo))
+    if total < 0:
+        raise RuntimeError("oracle_disassemble failed")
+    return buf[:min(total, int(text_cap))].tobytes(), tmo, int(total)

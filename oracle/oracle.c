@@ -423,3 +423,304 @@ int64_t oracle_encode(const uint16_t *op, const int32_t *opnd_off, const uint32_
   }
   return out;
 }
+
+/* ------------------------------------------------------------------------
+ * Disassembly to text (section "Dis/Assembler": the disassembler maps each
+ * opcode and operand of the binary back to text; its options listing names
+ * five switches, taken here in the listing's order as option bits
+ *   1 syntax highlight, 2 inline names, 4 no indentation, 8 grouping,
+ *   16 no header).
+ * The paper prints no text format beyond the disassembly of its capabilities
+ * example (one "OpCapability <name>" line per instruction), so the format
+ * below is this oracle's reading, written down in full:
+ *   - a module whose header check failed gives no text; otherwise the text
+ *     covers the instructions of its valid prefix (as decode's records);
+ *   - unless bit 16, five comment lines first: "; SPIR-V", "; Version: M.m",
+ *     "; Generator: g", "; Bound: b", "; Schema: 0" (decimal numbers);
+ *   - one line per instruction: [indent][%r = ]OpName[ operand]...\n where
+ *     the result ID (if the instruction has one) moves to the left of " = "
+ *     and the other operands keep their order; unless bit 4 the line is
+ *     padded on the left with spaces so that the opcode name starts at
+ *     column 15 (no padding if the "%r = " part is 15 characters or more);
+ *   - an ID prints as %<decimal>, or with bit 2 as %<name> when the first
+ *     OpName of the module that targets it carries a usable name (non-empty,
+ *     only [A-Za-z0-9_], not starting with a digit); names are not made
+ *     unique;
+ *   - a literal prints in decimal, or as its enumerant name where the operand
+ *     is an enumerant the table below knows (capability, addressing model,
+ *     memory model, execution model; function control as None or its bits
+ *     joined by '|'); an unknown value prints in decimal;
+ *   - a string prints between double quotes, with '"' and '\' escaped by a
+ *     backslash and every other byte as it is;
+ *   - bit 8 puts an empty line before every OpFunction and OpLabel;
+ *   - bit 1 wraps each opcode name, ID, literal and string token in an ANSI
+ *     colour (ESC[36m, ESC[33m, ESC[34m, ESC[32m) and ESC[0m; the padding is
+ *     counted without these codes.
+ * ------------------------------------------------------------------------ */
+
+enum { DIS_HIGHLIGHT = 1, DIS_INLINE_NAMES = 2, DIS_NO_INDENT = 4, DIS_GROUP = 8, DIS_NO_HEADER = 16 };
+
+typedef struct {
+  char *text;
+  int64_t cap, pos;
+} orc_out;
+
+static void put_byte(orc_out *o, char c) {
+  if (o->pos < o->cap) o->text[o->pos] = c;
+  ++o->pos;
+}
+
+static void put_str(orc_out *o, const char *s) {
+  while (*s) put_byte(o, *s++);
+}
+
+static void put_dec(orc_out *o, uint32_t v) {
+  char buf[12];
+  int k = 0;
+  do {
+    buf[k++] = (char)('0' + v % 10u);
+    v /= 10u;
+  } while (v);
+  while (k) put_byte(o, buf[--k]);
+}
+
+static const char *opcode_name(uint32_t op) {
+  switch (op) {
+    case 5: return "OpName";
+    case 14: return "OpMemoryModel";
+    case 15: return "OpEntryPoint";
+    case 17: return "OpCapability";
+    case 21: return "OpTypeInt";
+    case 43: return "OpConstant";
+    case 54: return "OpFunction";
+    case 56: return "OpFunctionEnd";
+    case 61: return "OpLoad";
+    case 62: return "OpStore";
+    case 128: return "OpIAdd";
+    case 248: return "OpLabel";
+    case 253: return "OpReturn";
+  }
+  return NULL;
+}
+
+/* Enumerant names of the SPIR-V specification for the literal operands of
+ * this grammar; NULL where the value is not in the table. */
+static const char *capability_name(uint32_t v) {
+  static const char *const names[] = {"Matrix",  "Shader",        "Geometry", "Tessellation", "Addresses",
+                                      "Linkage", "Kernel",        "Vector16", "Float16Buffer", "Float16",
+                                      "Float64", "Int64",         "Int64Atomics"};
+  if (v < sizeof(names) / sizeof(names[0])) return names[v];
+  if (v == 22) return "Int16";
+  if (v == 39) return "Int8";
+  return NULL;
+}
+
+static const char *addressing_name(uint32_t v) {
+  static const char *const names[] = {"Logical", "Physical32", "Physical64"};
+  return v < 3 ? names[v] : NULL;
+}
+
+static const char *memory_model_name(uint32_t v) {
+  static const char *const names[] = {"Simple", "GLSL450", "OpenCL", "Vulkan"};
+  return v < 4 ? names[v] : NULL;
+}
+
+static const char *execution_model_name(uint32_t v) {
+  static const char *const names[] = {"Vertex",   "TessellationControl", "TessellationEvaluation", "Geometry",
+                                      "Fragment", "GLCompute",           "Kernel"};
+  return v < 7 ? names[v] : NULL;
+}
+
+static void color_on(orc_out *o, uint32_t options, const char *code) {
+  if (options & DIS_HIGHLIGHT) {
+    put_byte(o, '\x1b');
+    put_byte(o, '[');
+    put_str(o, code);
+    put_byte(o, 'm');
+  }
+}
+
+static void color_off(orc_out *o, uint32_t options) {
+  if (options & DIS_HIGHLIGHT) put_str(o, "\x1b[0m");
+}
+
+/* The literal at operand slot s of opcode op. */
+static void put_literal(orc_out *o, uint32_t options, uint32_t op, uint32_t s, uint32_t v) {
+  const char *name = NULL;
+  if (op == 17) name = capability_name(v);
+  else if (op == 14) name = s == 0 ? addressing_name(v) : memory_model_name(v);
+  else if (op == 15) name = execution_model_name(v);
+  color_on(o, options, "34");
+  if (op == 54) { /* function control: a bit mask */
+    static const char *const bits[] = {"Inline", "DontInline", "Pure", "Const"};
+    if (v == 0) put_str(o, "None");
+    else if (v & ~0xFu) put_dec(o, v);
+    else {
+      int first = 1;
+      for (int b = 0; b < 4; ++b)
+        if (v & (1u << b)) {
+          if (!first) put_byte(o, '|');
+          put_str(o, bits[b]);
+          first = 0;
+        }
+    }
+  } else if (name) put_str(o, name);
+  else put_dec(o, v);
+  color_off(o, options);
+}
+
+/* A module's inline names: for each ID that some OpName targets, the first
+ * such OpName's string (module order). */
+typedef struct {
+  uint32_t id, order;
+  const uint8_t *name;
+} orc_name;
+
+static int cmp_name(const void *a, const void *b) {
+  const orc_name *x = (const orc_name *)a, *y = (const orc_name *)b;
+  if (x->id != y->id) return (x->id > y->id) - (x->id < y->id);
+  return (x->order > y->order) - (x->order < y->order);
+}
+
+static int usable_name(const uint8_t *s) {
+  if (s[0] == 0 || (s[0] >= '0' && s[0] <= '9')) return 0;
+  for (; *s; ++s)
+    if (!((*s >= 'a' && *s <= 'z') || (*s >= 'A' && *s <= 'Z') || (*s >= '0' && *s <= '9') || *s == '_'))
+      return 0;
+  return 1;
+}
+
+static const uint8_t *find_name(const orc_name *names, uint64_t n, uint32_t id) {
+  uint64_t lo = 0, hi = n;
+  while (lo < hi) {
+    uint64_t mid = (lo + hi) / 2;
+    if (names[mid].id < id) lo = mid + 1;
+    else hi = mid;
+  }
+  return (lo < n && names[lo].id == id) ? names[lo].name : NULL;
+}
+
+static void put_id(orc_out *o, uint32_t options, const orc_name *names, uint64_t n_names, uint32_t v) {
+  const uint8_t *name = (options & DIS_INLINE_NAMES) ? find_name(names, n_names, v) : NULL;
+  color_on(o, options, "33");
+  put_byte(o, '%');
+  if (name && usable_name(name)) put_str(o, (const char *)name);
+  else put_dec(o, v);
+  color_off(o, options);
+}
+
+/* Width of "%<token> = " without colour codes. */
+static int64_t lhs_width(uint32_t options, const orc_name *names, uint64_t n_names, uint32_t v) {
+  orc_out probe = {NULL, 0, 0};
+  put_id(&probe, options & ~(uint32_t)DIS_HIGHLIGHT, names, n_names, v);
+  return probe.pos + 3;
+}
+
+/* Text of every module of a CSR batch.  text receives the first
+ * min(total, text_cap) bytes of the whole text; text_mod_off (n_modules+1)
+ * the byte offsets where each module's text starts in it.  Returns the total
+ * number of bytes, or -1 on bad offsets or when memory for the names could
+ * not be had. */
+int64_t oracle_disassemble(const uint32_t *words, const int64_t *mod_off, int64_t n_modules, uint32_t options,
+                           char *text, int64_t text_cap, int64_t *text_mod_off) {
+  orc_out o = {text, text_cap, 0};
+  text_mod_off[0] = 0;
+  for (int64_t m = 0; m < n_modules; ++m) {
+    int64_t b = mod_off[m], e = mod_off[m + 1];
+    if (e < b) return -1;
+    const uint32_t *w = words + b;
+    uint64_t n = (uint64_t)(e - b);
+    orc_result r;
+    check_module(w, n, 0, 0, NULL, NULL, &r);
+    if (r.code != ORC_OK && r.code < ORC_BAD_WORD_COUNT) { /* header failed: no text */
+      text_mod_off[m + 1] = o.pos;
+      continue;
+    }
+    if (!(options & DIS_NO_HEADER)) {
+      put_str(&o, "; SPIR-V\n; Version: ");
+      put_dec(&o, (w[1] >> 16) & 0xFFu);
+      put_byte(&o, '.');
+      put_dec(&o, (w[1] >> 8) & 0xFFu);
+      put_str(&o, "\n; Generator: ");
+      put_dec(&o, w[2]);
+      put_str(&o, "\n; Bound: ");
+      put_dec(&o, w[3]);
+      put_str(&o, "\n; Schema: ");
+      put_dec(&o, w[4]);
+      put_byte(&o, '\n');
+    }
+    /* the names, first OpName per target */
+    orc_name *names = NULL;
+    uint64_t n_names = 0;
+    if (options & DIS_INLINE_NAMES) {
+      names = (orc_name *)malloc((r.n_inst + 1) * sizeof(orc_name));
+      if (!names) return -1;
+      uint64_t p = 5;
+      for (uint32_t j = 0; j < r.n_inst; ++j) {
+        if ((w[p] & 0xFFFFu) == 5) {
+          names[n_names].id = w[p + 1];
+          names[n_names].order = j;
+          names[n_names].name = (const uint8_t *)(w + p + 2);
+          ++n_names;
+        }
+        p += w[p] >> 16;
+      }
+      qsort(names, n_names, sizeof(orc_name), cmp_name);
+      uint64_t k = 0; /* keep the first of each id */
+      for (uint64_t i = 0; i < n_names; ++i)
+        if (k == 0 || names[k - 1].id != names[i].id) names[k++] = names[i];
+      n_names = k;
+    }
+    uint64_t p = 5;
+    for (uint32_t j = 0; j < r.n_inst; ++j) {
+      uint32_t wc = w[p] >> 16, op = w[p] & 0xFFFFu;
+      const orc_inst *g = lookup(op);
+      if (g == NULL || wc == 0 || p + wc > n) break; /* cannot happen inside the valid prefix */
+      uint32_t nfix = g->word_count == 0 ? fixed_operands(g) : wc - 1;
+      int has_result = 0;
+      uint32_t result = 0;
+      for (uint32_t s = 0; s < nfix; ++s)
+        if (g->roles[s] == 'D') {
+          has_result = 1;
+          result = w[p + 1 + s];
+        }
+      if ((options & DIS_GROUP) && (op == 54 || op == 248)) put_byte(&o, '\n');
+      if (!(options & DIS_NO_INDENT)) {
+        int64_t width = has_result ? lhs_width(options, names, n_names, result) : 0;
+        for (int64_t c = width; c < 15; ++c) put_byte(&o, ' ');
+      }
+      if (has_result) {
+        put_id(&o, options, names, n_names, result);
+        put_str(&o, " = ");
+      }
+      color_on(&o, options, "36");
+      put_str(&o, opcode_name(op));
+      color_off(&o, options);
+      for (uint32_t s = 0; s < nfix; ++s) {
+        char role = g->roles[s];
+        uint32_t v = w[p + 1 + s];
+        if (role == 'D') continue;
+        put_byte(&o, ' ');
+        if (role == 'U') put_id(&o, options, names, n_names, v);
+        else put_literal(&o, options, op, s, v);
+      }
+      if (g->word_count == 0) { /* the string, validated by the parse stage */
+        const uint8_t *s = (const uint8_t *)(w + p + 1 + nfix);
+        put_byte(&o, ' ');
+        color_on(&o, options, "32");
+        put_byte(&o, '"');
+        for (; *s; ++s) {
+          if (*s == '"' || *s == '\\') put_byte(&o, '\\');
+          put_byte(&o, (char)*s);
+        }
+        put_byte(&o, '"');
+        color_off(&o, options);
+      }
+      put_byte(&o, '\n');
+      p += wc;
+    }
+    free(names);
+    text_mod_off[m + 1] = o.pos;
+  }
+  return o.pos;
+}

@@ -144,3 +144,107 @@ def encode_module(records, version_word=0x00010600, generator_word=0):
         body.extend(struct.unpack("<%dI" % (len(sw) // 4), sw))
     bound = max(ids) + 1 if ids else 1
     return [0x07230203, version_word, generator_word, bound, 0] + body
+
+
+# --- disassembly to text (section "Dis/Assembler"; the options listing's
+# five switches as bits 1 highlight, 2 inline names, 4 no indentation,
+# 8 grouping, 16 no header).  A second statement of the text format of
+# oracle.c, built from token lists instead of a byte writer.
+
+NAMES = {5: "OpName", 14: "OpMemoryModel", 15: "OpEntryPoint", 17: "OpCapability", 21: "OpTypeInt",
+         43: "OpConstant", 54: "OpFunction", 56: "OpFunctionEnd", 61: "OpLoad", 62: "OpStore", 128: "OpIAdd",
+         248: "OpLabel", 253: "OpReturn"}
+# enumerants (SPIR-V specification) of the literal operands, by (opcode, operand slot)
+ENUMS = {
+    (17, 0): {0: "Matrix", 1: "Shader", 2: "Geometry", 3: "Tessellation", 4: "Addresses", 5: "Linkage",
+              6: "Kernel", 7: "Vector16", 8: "Float16Buffer", 9: "Float16", 10: "Float64", 11: "Int64",
+              12: "Int64Atomics", 22: "Int16", 39: "Int8"},
+    (14, 0): {0: "Logical", 1: "Physical32", 2: "Physical64"},
+    (14, 1): {0: "Simple", 1: "GLSL450", 2: "OpenCL", 3: "Vulkan"},
+    (15, 0): {0: "Vertex", 1: "TessellationControl", 2: "TessellationEvaluation", 3: "Geometry",
+              4: "Fragment", 5: "GLCompute", 6: "Kernel"},
+}
+COLOR = {"op": 36, "id": 33, "lit": 34, "str": 32}
+
+
+def _function_control(v):
+    if v == 0:
+        return "None"
+    if v >> 4:
+        return str(v)
+    return "|".join(n for b, n in enumerate(("Inline", "DontInline", "Pure", "Const")) if v >> b & 1)
+
+
+def _name_ok(name: bytes) -> bool:
+    return bool(name) and not name[:1].isdigit() and all(
+        c in b"abcdefghijklmnopqrstuvwxyzABCDEFGHIJKLMNOPQRSTUVWXYZ0123456789_" for c in name)
+
+
+def disassemble_module(words, options: int = 0) -> bytes:
+    """Text of one module (bytes); empty when its header check fails."""
+    w = [int(x) & 0xFFFFFFFF for x in words]
+    code, _, _, _, insts = check(w, semantic=False)
+    if 1 <= code <= 4:
+        return b""
+    raw = struct.pack("<%dI" % len(w), *w)
+
+    def string_at(word_pos):
+        b = raw[4 * word_pos:]
+        return b[:b.index(b"\x00")]
+
+    names = {}
+    if options & 2:
+        for pos, opcode in insts:
+            if opcode == 5:
+                names.setdefault(w[pos + 1], string_at(pos + 2))
+
+    def tok(kind, text):
+        return (kind, text)
+
+    def id_tok(v):
+        nm = names.get(v)
+        return tok("id", "%" + (nm.decode() if nm is not None and _name_ok(nm) else str(v)))
+
+    lines = []
+    if not options & 16:
+        lines.append([tok(None, "; SPIR-V")])
+        lines.append([tok(None, "; Version: %d.%d" % (raw[6], raw[5]))])
+        lines.append([tok(None, "; Generator: %d" % w[2])])
+        lines.append([tok(None, "; Bound: %d" % w[3])])
+        lines.append([tok(None, "; Schema: %d" % w[4])])
+    for pos, opcode in insts:
+        kinds = KINDS[opcode]
+        left, right = [], []
+        for slot, kind in enumerate(kinds):
+            if kind == "str":
+                s = string_at(pos + 1 + slot).decode("latin-1")
+                s = s.replace("\\", "\\\\").replace('"', '\\"')
+                right.append(tok("str", '"' + s + '"'))
+                continue
+            v = w[pos + 1 + slot]
+            if kind == "result":
+                left = [id_tok(v), tok(None, " = ")]
+            elif kind == "id":
+                right.append(id_tok(v))
+            elif opcode == 54:
+                right.append(tok("lit", _function_control(v)))
+            else:
+                right.append(tok("lit", ENUMS.get((opcode, slot), {}).get(v, str(v))))
+        if options & 8 and opcode in (54, 248):
+            lines.append([])
+        line = []
+        if not options & 4:
+            width = sum(len(t) for _, t in left)
+            line.append(tok(None, " " * max(0, 15 - width)))
+        line += left + [tok("op", NAMES[opcode])]
+        for t in right:
+            line += [tok(None, " "), t]
+        lines.append(line)
+    out = []
+    for line in lines:
+        for kind, text in line:
+            if kind is not None and options & 1:
+                text = "\x1b[%dm%s\x1b[0m" % (COLOR[kind], text)
+            out.append(text)
+        out.append("\n")
+    return "".join(out).encode("latin-1")

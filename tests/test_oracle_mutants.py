@@ -54,6 +54,22 @@ MUTANTS = [
     ("encode little-endian swapped", "word |= byte << (8 * b);", "word |= byte << (8 * (3 - b));"),
     ("encode failed module keeps its header", "    if (code != ORC_ENC_OK) {\n      word_mod_off[m + 1] = out;",
      "    if (code != ORC_ENC_OK) {\n      word_mod_off[m + 1] = out + 5;"),
+    ("text: opcode column 14", "for (int64_t c = width; c < 15; ++c)", "for (int64_t c = width; c < 14; ++c)"),
+    ("text: last OpName wins", "if (k == 0 || names[k - 1].id != names[i].id) names[k++] = names[i];",
+     "if (k > 0 && names[k - 1].id == names[i].id) names[k - 1] = names[i];\n        else names[k++] = names[i];"),
+    ("text: digit-led names inlined", "if (s[0] == 0 || (s[0] >= '0' && s[0] <= '9')) return 0;",
+     "if (s[0] == 0) return 0;"),
+    ("text: quote not escaped", "if (*s == '\"' || *s == '\\\\') put_byte(&o, '\\\\');",
+     "if (*s == '\\\\') put_byte(&o, '\\\\');"),
+    ("text: no group line before OpLabel", "(op == 54 || op == 248)) put_byte(&o, '\\n');",
+     "(op == 54)) put_byte(&o, '\\n');"),
+    ("text: version fields swapped", "put_dec(&o, (w[1] >> 16) & 0xFFu);", "put_dec(&o, (w[1] >> 8) & 0xFFu);"),
+    ("text: memory model operands swapped", "name = s == 0 ? addressing_name(v) : memory_model_name(v);",
+     "name = s == 0 ? memory_model_name(v) : addressing_name(v);"),
+    ("text: padding counts colour codes", "put_id(&probe, options & ~(uint32_t)DIS_HIGHLIGHT,",
+     "put_id(&probe, options,"),
+    ("text: result kept among the operands", "if (role == 'D') continue;", "if (0) continue;"),
+    ("text: function control bits reversed", "if (v & (1u << b)) {", "if (v & (8u >> b)) {"),
 ]
 
 
@@ -87,6 +103,11 @@ def _battery():
         checks.append((f"rules {len(parts)}", lambda p=parts, e=expect: rules.test_rules_on_valid_modules(p, e)))
     for ent, expect in [m.args for m in rules.test_entry_point_forms.pytestmark if m.name == "parametrize"][0][1]:
         checks.append((f"entry {ent[0]:#x}", lambda a=ent, e=expect: rules.test_entry_point_forms(a, e)))
+    import test_oracle_disasm as dis
+    for case in dis.CASES:
+        checks.append((f"text {case['name']}", lambda c=case: dis.test_golden_disassembly(c)))
+    checks.append(("text random", dis.test_random_tiny_modules_agree_with_second_statement))
+    checks.append(("text batch", dis.test_batch_offsets_and_truncation))
     for name, fn in checks:
         try:
             fn()
@@ -107,7 +128,7 @@ def test_mutant_is_caught(name, old, new, tmp_path):
     import ctypes
     real = oracle._load()
     mut = ctypes.CDLL(str(so))
-    for fn in ("oracle_validate", "oracle_records", "oracle_encode_bound", "oracle_encode"):
+    for fn in ("oracle_validate", "oracle_records", "oracle_encode_bound", "oracle_encode", "oracle_disassemble"):
         getattr(mut, fn).argtypes = getattr(real, fn).argtypes
         getattr(mut, fn).restype = getattr(real, fn).restype
     try:
