@@ -210,6 +210,57 @@ int spv_decode_records(spv_ctx *ctx, const uint32_t *words, const int64_t *mod_o
                        int32_t *opnd_off, uint32_t *opnd, int32_t *str_off, uint8_t *chars, int64_t *rec_mod_off,
                        void *ws, size_t ws_bytes, void *stream);
 
+/* Options of spv_decode_text: the five switches of the disassembler's
+ * options listing (section "Dis/Assembler"), in the listing's order. */
+#define SPV_TEXT_HIGHLIGHT 1u    /* ANSI colours: opcode 36, IDs 33, literals 34, strings 32, reset 0 */
+#define SPV_TEXT_INLINE_NAMES 2u /* %<name> for IDs that an OpName names */
+#define SPV_TEXT_NO_INDENT 4u    /* no padding to column 15 */
+#define SPV_TEXT_GROUP 8u        /* an empty line before each OpFunction and OpLabel */
+#define SPV_TEXT_NO_HEADER 16u   /* no "; SPIR-V" header comment lines */
+
+/* Bytes of workspace spv_decode_text needs (it depends on
+ * SPV_TEXT_INLINE_NAMES: about 4 bytes per word without it, up to 32 with it). */
+int spv_text_workspace_size(spv_ctx *ctx, int64_t n_modules, int64_t n_words, uint32_t options, size_t *bytes);
+
+/* Decode's text mode: disassembly of the instructions a spv_decode /
+ * spv_validate call found into SPIR-V assembly text (section "Dis/Assembler":
+ * opcodes and operands mapped back to text, under the five switches of its
+ * options listing).  Module m's text covers its valid instruction prefix
+ * (results[m].n_inst instructions), or is empty when its header check failed
+ * (codes 1..4).  The format:
+ *   - unless SPV_TEXT_NO_HEADER: "; SPIR-V", "; Version: M.m",
+ *     "; Generator: g", "; Bound: b", "; Schema: s" lines (decimal);
+ *   - one line per instruction: [padding][%r = ]OpName[ operand]..."\n";
+ *     the result ID moves left of " = " and the other operands keep their
+ *     order; unless SPV_TEXT_NO_INDENT, spaces pad the line so that the
+ *     opcode name starts at column 15 (none if "%r = " is 15 or wider);
+ *   - IDs print as %<decimal>; with SPV_TEXT_INLINE_NAMES as %<name> when
+ *     the module's first OpName of the ID has a usable name (non-empty, only
+ *     [A-Za-z0-9_], not starting with a digit; not made unique);
+ *   - literals print in decimal, or as their SPIR-V enumerant for the
+ *     capability, addressing model, memory model and execution model operands
+ *     of the table, and the function control mask as None or its bits
+ *     (Inline|DontInline|Pure|Const) joined by '|';
+ *   - strings print in double quotes with '"' and '\' escaped by '\';
+ *   - SPV_TEXT_GROUP: an empty line before each OpFunction and OpLabel;
+ *   - SPV_TEXT_HIGHLIGHT: ESC[3Xm ... ESC[0m around each opcode name, ID,
+ *     literal and string (padding counts visible characters only).
+ *   words, mod_off, idx_off, results : the batch and the index and results of
+ *     the decode call made on it (the module rules code 11 counts as decoded)
+ *   text : device buffer of text_cap bytes, 4-byte aligned; it receives the
+ *     first min(total, text_cap) bytes of the whole text (a text_cap of 0 only
+ *     sizes it)
+ *   text_mod_off : int64[n_modules+1] device buffer; module m's text is
+ *     text[text_mod_off[m] .. text_mod_off[m+1]), text_mod_off[n_modules] is
+ *     the total; a module is complete in text iff text_mod_off[m+1] <=
+ *     text_cap (all -1 if a kernel's wait exceeded its spin limit)
+ * Asynchronous on stream; SPV_ERR_INVALID_ARG for unknown option bits or a
+ * misaligned text, SPV_ERR_LIMIT for n_words >= 2^29 or n_modules >= 2^26,
+ * SPV_ERR_WORKSPACE when ws is smaller than spv_text_workspace_size. */
+int spv_decode_text(spv_ctx *ctx, const uint32_t *words, const int64_t *mod_off, int64_t n_modules, int64_t n_words,
+                    const uint32_t *idx_off, const spv_result *results, uint32_t options, uint8_t *text,
+                    int64_t text_cap, int64_t *text_mod_off, void *ws, size_t ws_bytes, void *stream);
+
 /* Host-side upper bound on the words spv_encode may write:
  * 5*n_modules + n_records + n_opnd_words + n_string_records + n_chars/4. */
 int spv_encode_bound(int64_t n_modules, int64_t n_records, int64_t n_opnd_words, int64_t n_string_records,

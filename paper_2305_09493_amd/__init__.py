@@ -64,11 +64,14 @@ def load_library():
         lib.spv_encode.argtypes = [P, P, P, P, P, P, P, I64, I64, U32, U32, P, P, I64, P, P, P, SZ, P]
         lib.spv_records_workspace_size.argtypes = [P, I64, I64, ctypes.POINTER(SZ)]
         lib.spv_decode_records.argtypes = [P, P, P, I64, I64, P, P, P, P, P, P, P, P, P, SZ, P]
+        lib.spv_text_workspace_size.argtypes = [P, I64, I64, U32, ctypes.POINTER(SZ)]
+        lib.spv_decode_text.argtypes = [P, P, P, I64, I64, P, P, U32, P, I64, P, P, SZ, P]
         lib.spv_set_timing.argtypes = [P, ctypes.c_int]
         lib.spv_get_tuning.argtypes = [P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
         lib.spv_read_timing.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)]
         for name in ("spv_create", "spv_destroy", "spv_set_tuning", "spv_workspace_size", "spv_decode",
                      "spv_validate", "spv_validate_noalloc", "spv_encode_bound", "spv_encode_workspace_size", "spv_encode",
+                     "spv_records_workspace_size", "spv_decode_records", "spv_text_workspace_size", "spv_decode_text",
                      "spv_set_timing", "spv_read_timing", "spv_get_tuning", "spv_server_create", "spv_server_start", "spv_server_submit",
            "spv_server_poll", "spv_server_stats", "spv_server_destroy", "spv_server_cancel"):
             getattr(lib, name).restype = ctypes.c_int
@@ -78,7 +81,7 @@ def load_library():
 
 EXPORTS = ("spv_create", "spv_destroy", "spv_last_hip_error", "spv_set_tuning", "spv_workspace_size",
            "spv_decode", "spv_validate", "spv_validate_noalloc", "spv_encode_bound", "spv_encode_workspace_size", "spv_encode",
-           "spv_records_workspace_size", "spv_decode_records",
+           "spv_records_workspace_size", "spv_decode_records", "spv_text_workspace_size", "spv_decode_text",
            "spv_set_timing", "spv_read_timing", "spv_get_tuning", "spv_server_create", "spv_server_start", "spv_server_submit",
            "spv_server_poll", "spv_server_stats", "spv_server_destroy", "spv_server_cancel")
 
@@ -296,6 +299,47 @@ def encode(op, opnd_off, opnd, str_off, chars, rec_mod_off, version_word: int = 
                             words_cap, _ptr(code), _ptr(bad), _ptr(ws), ws.numel(), _stream(stream))
     ctx.check(rc, "spv_encode")
     return words, word_mod_off, code, bad
+
+
+# options of decode_text: the disassembler's five switches, in its options listing's order
+TEXT_HIGHLIGHT, TEXT_INLINE_NAMES, TEXT_NO_INDENT, TEXT_GROUP, TEXT_NO_HEADER = 1, 2, 4, 8, 16
+
+
+def decode_text(words, mod_off, idx_off, results, options: int = 0, text=None, ctx: Optional[Context] = None,
+                stream=None):
+    """Decode's text mode: SPIR-V assembly text of every module's valid
+    instruction prefix, from the index and results of a decode / validate
+    call on the same batch.  With ``text`` (a 4-byte aligned CUDA uint8
+    tensor), one asynchronous call fills it with the first min(total,
+    text.numel()) bytes; without it, a sizing call and a host read of the
+    total come first.  Returns (text, text_mod_off): module m's text is
+    text[text_mod_off[m]:text_mod_off[m+1]]; text_mod_off[-1] is the total."""
+    torch = _torch()
+    ctx = ctx or context(words.device.index)
+    dev = words.device
+    W = int(words.numel())
+    M = int(mod_off.numel()) - 1
+    tmo = torch.empty(M + 1, dtype=torch.int64, device=dev)
+    sz = ctypes.c_size_t()
+    ctx.check(ctx.lib.spv_text_workspace_size(ctx.h, M, W, options, ctypes.byref(sz)), "spv_text_workspace_size")
+    ws = ctx.workspace(sz.value)
+
+    def call(buf, cap):
+        rc = ctx.lib.spv_decode_text(ctx.h, _ptr(words), _ptr(mod_off), M, W, _ptr(idx_off), _ptr(results),
+                                     options, _ptr(buf) if buf is not None else None, cap, _ptr(tmo), _ptr(ws),
+                                     ws.numel(), _stream(stream))
+        ctx.check(rc, "spv_decode_text")
+
+    if text is None:
+        call(None, 0)
+        total = int(tmo[-1].item()) if M > 0 else 0
+        if total < 0:
+            raise SpvError("spv_decode_text: a kernel's wait exceeded its spin limit")
+        text = torch.empty(max(total, 4), dtype=torch.uint8, device=dev)
+    elif text.dtype != torch.uint8 or not text.is_cuda or text.data_ptr() % 4:
+        raise SpvError("text must be a 4-byte aligned CUDA uint8 tensor")
+    call(text, int(text.numel()))
+    return text, tmo
 
 
 def decode_records(words, mod_off, idx_off, results, ctx: Optional[Context] = None, stream=None):

@@ -380,6 +380,51 @@ int spv_decode_records(spv_ctx* ctx, const uint32_t* words, const int64_t* mod_o
   return check_launch(ctx);
 }
 
+int spv_text_workspace_size(spv_ctx* ctx, int64_t n_modules, int64_t n_words, uint32_t options, size_t* bytes) {
+  if (!ctx || !bytes || n_modules < 0 || n_words < 0 || (options & ~31u)) return SPV_ERR_INVALID_ARG;
+  *bytes = spv::make_tlayout(n_modules, n_words, options).total;
+  return SPV_SUCCESS;
+}
+
+int spv_decode_text(spv_ctx* ctx, const uint32_t* words, const int64_t* mod_off, int64_t n_modules, int64_t n_words,
+                    const uint32_t* idx_off, const spv_result* results, uint32_t options, uint8_t* text,
+                    int64_t text_cap, int64_t* text_mod_off, void* ws, size_t ws_bytes, void* stream) {
+  if (!ctx || n_modules < 0 || n_words < 0 || text_cap < 0 || (options & ~31u)) return SPV_ERR_INVALID_ARG;
+  if (n_words >= (int64_t(1) << 29)) return SPV_ERR_LIMIT;     // instruction counts fit 29 bits
+  if (n_modules >= (int64_t(1) << 26)) return SPV_ERR_LIMIT;   // header bytes of all modules fit 33 bits
+  if (n_modules == 0) return n_words == 0 ? SPV_SUCCESS : SPV_ERR_INVALID_ARG;
+  if (!mod_off || !results || !text_mod_off) return SPV_ERR_INVALID_ARG;
+  if (n_words > 0 && (!words || !idx_off)) return SPV_ERR_INVALID_ARG;
+  if (text_cap > 0 && (!text || (reinterpret_cast<uintptr_t>(text) & 3u))) return SPV_ERR_INVALID_ARG;
+  spv::TLayout L = spv::make_tlayout(n_modules, n_words, options);
+  if (!ws || ws_bytes < L.total) return SPV_ERR_WORKSPACE;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail_hip(ctx, hipErrorInvalidDevice);
+  char* base = static_cast<char*>(ws);
+  spv::TParams p;
+  p.words = words;
+  p.mod_off = mod_off;
+  p.M = n_modules;
+  p.cap_inst = n_words;
+  p.idx_off = idx_off;
+  p.results = results;
+  p.options = options;
+  p.text = text;
+  p.text_cap = text_cap;
+  p.text_mod_off = text_mod_off;
+  p.ctrl = reinterpret_cast<uint32_t*>(base + L.ctrl);
+  p.mscan = reinterpret_cast<unsigned long long*>(base + L.mscan);
+  p.mstate = reinterpret_cast<unsigned long long*>(base + L.mstate);
+  p.lens = reinterpret_cast<uint32_t*>(base + L.lens);
+  p.btot = reinterpret_cast<unsigned long long*>(base + L.btot);
+  p.bstate = reinterpret_cast<unsigned long long*>(base + L.bstate);
+  p.slots = reinterpret_cast<spv::TxtSlot*>(base + L.slots);
+  p.slot_cap = L.slot_cap;
+  p.nlist = reinterpret_cast<uint2*>(base + L.nlist);
+  spv::launch_text(p, static_cast<hipStream_t>(stream));
+  return check_launch(ctx);
+}
+
 int spv_encode_workspace_size(spv_ctx* ctx, int64_t n_modules, int64_t n_records, size_t* bytes) {
   if (!ctx || !bytes || n_modules < 0 || n_records < 0) return SPV_ERR_INVALID_ARG;
   *bytes = spv::make_elayout(n_modules, n_records, ctx->encode_block).total;

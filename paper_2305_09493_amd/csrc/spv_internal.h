@@ -306,4 +306,77 @@ inline RLayout make_rlayout(int64_t n_modules, int64_t n_words) {
 
 void launch_records(const RParams& p, hipStream_t s);
 
+// decode's text mode (disassembly to text)
+enum : uint32_t {
+  kTxtHighlight = 1u,
+  kTxtInlineNames = 2u,
+  kTxtNoIndent = 4u,
+  kTxtGroup = 8u,
+  kTxtNoHeader = 16u,
+};
+// Inline-name hash slot: key (module << 32 | target ID), the word position
+// of the module's first OpName of that target (atomicMin), and the length of
+// its name when usable (0 = print the number).
+struct TxtSlot {
+  unsigned long long key;
+  uint32_t pos;
+  uint32_t len;
+};
+constexpr unsigned long long kTxtEmpty = ~0ull;
+struct TParams {
+  const uint32_t* words;
+  const int64_t* mod_off;
+  int64_t M;
+  int64_t cap_inst;  // n_words: no batch has more instructions
+  const uint32_t* idx_off;
+  const spv_result* results;
+  uint32_t options;
+  uint8_t* text;
+  int64_t text_cap;
+  int64_t* text_mod_off;
+  // workspace
+  uint32_t* ctrl;               // 0, 1: scan claims; 2: a scan gave up waiting; 3: OpName count
+  unsigned long long* mscan;    // per module: header bytes << 29 | instructions, then the exclusive scan
+  unsigned long long* mstate;   // look-back states of the module scan
+  uint32_t* lens;               // per instruction: line bytes; after the scatter, offset in its block
+  unsigned long long* btot;     // per block of 1024 instructions: bytes, then the exclusive scan
+  unsigned long long* bstate;   // look-back states of the block scan
+  TxtSlot* slots;               // inline-name hash (slot_cap slots, a power of two)
+  int64_t slot_cap;
+  uint2* nlist;                 // OpName instructions: (module, word position)
+};
+struct TLayout {
+  size_t ctrl, mscan, mstate, lens, btot, bstate, slots, nlist, total;
+  int64_t slot_cap;
+};
+inline TLayout make_tlayout(int64_t n_modules, int64_t n_words, uint32_t options) {
+  TLayout L;
+  size_t off = 0;
+  L.ctrl = off;
+  off = align256(off + 256);
+  L.mscan = off;
+  off = align256(off + 8 * size_t(n_modules + 1));
+  L.mstate = off;
+  off = align256(off + 128 * size_t((n_modules + 1) / 1024 + 2));
+  L.lens = off;
+  off = align256(off + 4 * size_t(n_words + 1));
+  const int64_t nb = n_words / 1024 + 1;  // blocks of 1024 instructions, at most
+  L.btot = off;
+  off = align256(off + 8 * size_t(nb + 1));
+  L.bstate = off;
+  off = align256(off + 128 * size_t(nb / 1024 + 2));
+  // an OpName has at least 3 words
+  const int64_t max_names = (options & kTxtInlineNames) ? n_words / 3 + 1 : 0;
+  int64_t cap = 64;
+  while (cap < 2 * max_names) cap <<= 1;
+  L.slot_cap = (options & kTxtInlineNames) ? cap : 0;
+  L.slots = off;
+  off = align256(off + sizeof(TxtSlot) * size_t(L.slot_cap));
+  L.nlist = off;
+  off = align256(off + 8 * size_t(max_names));
+  L.total = off;
+  return L;
+}
+void launch_text(const TParams& p, hipStream_t s);
+
 }  // namespace spv

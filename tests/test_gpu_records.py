@@ -99,3 +99,30 @@ def test_records_long_names_and_round_trip():
     g2, _ = _check(b.words, b.mod_off, "generated for round trip")
     ow2, omo2, oc2, _ = oracle.encode(**g2)
     assert not oc2.any() and np.array_equal(ow2, b.words) and np.array_equal(omo2, b.mod_off)
+
+
+def test_records_after_validate_with_rules():
+    """A module that fails only the module rules (code 11) was decoded in full:
+    its records are all of its instructions."""
+    import torch
+
+    import paper_2305_09493_amd as spv
+    mods = [spvgen.gen_module([43, i], 200) for i in range(5)]
+    b = spvgen.pack(mods)
+    w = b.words.copy()
+    _, io, iop = oracle.validate(w, b.mod_off)
+    base = int(b.mod_off[1])
+    for j in range(200):  # module 1 loses every OpCapability (each becomes two OpReturns)
+        if iop[base + j] == 17:
+            p = base + int(io[base + j])
+            w[p], w[p + 1] = 0x000100FD, 0x000100FD
+    print("[records parity] after validate with the module rules", flush=True)
+    dw, dmo = to_dev(w, b.mod_off)
+    res, dio, _ = spv.validate(dw, dmo, module_rules=True)
+    rec = spv.decode_records(dw, dmo, dio, res)
+    torch.cuda.synchronize()
+    assert int(res[1, 0].item()) == oracle.E_MODULE_RULES
+    o = oracle.records(w, b.mod_off)
+    assert np.array_equal(rec["rec_mod_off"].cpu().numpy(), o["rec_mod_off"])
+    n = int(o["rec_mod_off"][-1])
+    assert np.array_equal(rec["op"].cpu().numpy().view(np.uint16)[:n], o["op"])
