@@ -19,14 +19,22 @@ Also reported on the same JSON line:
                 walk), against 8 TB/s; traffic: HBM bytes per call from the
                 committed rocprofv3 counter summary, when it was taken on
                 the current kernel code;
-  cpu_baseline  the CPU oracle (single thread) on the same module;
+  cpu_baseline  the CPU oracle on the same module (one module is one
+                sequential walk: one core), with the host CPU model;
+  copy_ceiling  what a plain device copy reaches (read + write GB/s);
   batched       4096 lognormal modules with 41 injected faults per launch
-                (graph replays of one captured call): words/s and p50 / p99
-                per-launch latency.
-Optional legs: --encode (10M records in 1024 modules), --records (decode's
-records mode on the timed module), --module-rules (the validate call with
-the module-level rules), --serve (Poisson stream, batched vs one module per
-launch).
+                (graph replays of one captured call): words/s, p50 / p99
+                per-launch latency, its roofline, and the oracle on the same
+                batch module-parallel on every host thread (at most 16);
+  records       decode's records mode on the timed module;
+  text          decode's text mode (disassembly) of the timed module, with
+                the paper's listing options (11) and with none (0);
+  module_rules  the validate call with the module-level rules;
+  encode        10M records in 1024 modules;
+  serving       Poisson stream at 20k modules/s, batched vs one module per
+                launch.
+Each leg after the first has a --no-<leg> switch; --only-main keeps only the
+timed call.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -175,6 +183,111 @@ def records_leg(ctx, words, mod_off, idx_off, res, W, steps=10):
             "hbm_frac": bytes_moved / dt / 1e9 / HBM_PEAK_GBS}
 
 
+def text_leg(ctx, words, mod_off, idx_off, res, W, n_inst, options_list=(11, 0), steps=10):
+    """Decode's text mode (disassembly to text) on the timed module, from the
+    index of the timed call: per option set, the text bytes, the time of one
+    call (graph replays of the captured call between two HIP events on the
+    replay stream) and the algorithmic bytes (words and index read, text
+    written) per second.  Options 11 are the paper's options listing
+    (highlight, inline names, indentation, grouping, header)."""
+    import torch
+
+    import paper_2305_09493_amd as spv
+    out = []
+    for options in options_list:
+        text, tmo = spv.decode_text(words, mod_off, idx_off, res, options, ctx=ctx)  # sizing call + fill
+        torch.cuda.synchronize()
+        total = int(tmo[-1].item())
+        graph, gs = torch.cuda.CUDAGraph(), torch.cuda.Stream()
+        with torch.cuda.stream(gs):
+            with torch.cuda.graph(graph, stream=gs):
+                spv.decode_text(words, mod_off, idx_off, res, options, text=text, ctx=ctx, stream=gs)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        rs = torch.cuda.current_stream()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(rs)
+        for _ in range(steps):
+            graph.replay()
+        ev1.record(rs)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / steps
+        algo = 4.0 * W + 4.0 * n_inst + total
+        out.append({"options": options, "text_bytes": total, "ms_per_call": ms,
+                    "words_per_s": W / (ms / 1e3), "lines_per_s": n_inst / (ms / 1e3),
+                    "algorithmic_bytes": algo, "algorithmic_GBps": algo / (ms / 1e3) / 1e9,
+                    "hbm_frac": algo / (ms / 1e3) / 1e9 / HBM_PEAK_GBS})
+        del graph, text
+        torch.cuda.empty_cache()
+    return out
+
+
+def copy_ceiling(dev, n_bytes=1 << 30, steps=10):
+    """What a plain device-to-device copy (torch's copy kernel) reaches on this
+    GPU: read + write bytes per second, timed with HIP events."""
+    import torch
+    src = torch.ones(n_bytes // 4, dtype=torch.int32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(steps):
+        dst.copy_(src)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * n_bytes / (ms / 1e3) / 1e9
+
+
+def host_threads():
+    """Host threads this process may use (the CPU share, at most 16)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_parallel(words, mod_off, threads):
+    """The oracle's validate over a batch, module-parallel: contiguous groups
+    of modules of about equal words, one group per host thread (the oracle's
+    C code runs without the GIL).  Returns (seconds, results)."""
+    import concurrent.futures as cf
+
+    import oracle
+    M = mod_off.size - 1
+    cuts = np.searchsorted(mod_off, np.linspace(0, mod_off[-1], threads + 1)).clip(0, M)
+    cuts[0], cuts[-1] = 0, M
+    cuts = np.unique(cuts)
+
+    def run(a, b):
+        lo, hi = int(mod_off[a]), int(mod_off[b])
+        return oracle.validate(words[lo:hi], mod_off[a:b + 1] - lo, index=False)
+
+    oracle.validate(words[:int(mod_off[1])], mod_off[:2], index=False)  # build / load outside the timing
+    t = time.perf_counter()
+    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        parts = list(ex.map(lambda ab: run(*ab), zip(cuts[:-1], cuts[1:])))
+    dt = time.perf_counter() - t
+    return dt, np.concatenate(parts)
+
+
 def rules_leg(ctx, words, mod_off, plain_ms, steps=10):
     """The validate call with the module-level rules (a capability, the
     memory model, a function, an entry point) as a last stage, on the timed
@@ -241,18 +354,23 @@ def main():
     ap.add_argument("--no-check", action="store_true", help="skip the full-size parity check")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--cache", default=None, help="npy file to keep the generated module between runs")
-    ap.add_argument("--encode", action="store_true", help="add the encode leg (10M records, 1024 modules)")
-    ap.add_argument("--records", action="store_true", help="add the records-mode leg (records of the timed module)")
-    ap.add_argument("--module-rules", action="store_true",
-                    help="add the leg of the validate call with the module-level rules")
-    ap.add_argument("--serve", action="store_true", help="add the serving leg (Poisson stream, batched vs "
-                                                         "one module per launch)")
+    ap.add_argument("--no-encode", action="store_true", help="skip the encode leg (10M records, 1024 modules)")
+    ap.add_argument("--no-records", action="store_true", help="skip the records-mode leg")
+    ap.add_argument("--no-text", action="store_true", help="skip the text-mode (disassembly) leg")
+    ap.add_argument("--no-module-rules", action="store_true",
+                    help="skip the leg of the validate call with the module-level rules")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg (Poisson stream, batched vs "
+                                                            "one module per launch)")
+    ap.add_argument("--only-main", action="store_true", help="only the timed validate call (no other leg)")
     ap.add_argument("--serve-rates", default="20000", help="comma-separated arrival rates for --serve")
     ap.add_argument("--serve-seconds", type=float, default=3.0, help="measured seconds per rate")
     ap.add_argument("--serve-warmup", type=float, default=1.0,
                     help="seconds of arrivals served before the measured ones and left out of p50/p99")
     ap.add_argument("--serve-pool", type=int, default=2048)
     args = ap.parse_args()
+    if args.only_main:
+        args.no_cpu = args.no_batched = args.no_encode = args.no_records = args.no_text = True
+        args.no_module_rules = args.no_serve = True
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path (batches would shard by a "
@@ -366,9 +484,11 @@ def main():
             if not ok:
                 log(f"PARITY FAILURE: gpu {g} oracle {exp}")
         if not args.no_cpu:
-            cpu = {"value": W / t_cpu, "unit": "words/s", "cores": 1, "kind": "oracle",
+            cpu = {"value": W / t_cpu, "unit": "words/s", "cores": 1, "kind": "oracle", "cpu_model": cpu_model(),
+                   "host_threads": host_threads(),
                    "sample": f"the full timed module ({W} words), validate with index, one pass "
-                             f"({t_cpu:.2f} s)"}
+                             f"({t_cpu:.2f} s); one module is one sequential walk, so one core (the "
+                             f"batched leg runs the oracle module-parallel on every host thread)"}
 
     batched = None
     if not args.no_batched:
@@ -404,15 +524,40 @@ def main():
         torch.cuda.synchronize()
         tb1 = time.perf_counter()
         lat = np.array([a.elapsed_time(b) for a, b in ev])
-        faults = int(np.sum(r3.cpu().numpy()[:, 0] != 0))
-        batched = {"modules": M3, "words": W3, "words_per_s": W3 * n_rep / (tb1 - tb0),
+        g3res = r3.cpu().numpy().view(np.uint32)
+        faults = int(np.sum(g3res[:, 0] != 0))
+        n3 = int(np.sum(g3res[:, 3]))
+        algo3 = 4.0 * W3 + 6.0 * n3
+        mean_ms = float(np.mean(lat))
+        batched = {"modules": M3, "words": W3, "instructions": n3, "words_per_s": W3 * n_rep / (tb1 - tb0),
                    "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-                   "modules_flagged": faults, "launches": n_rep}
+                   "modules_flagged": faults, "launches": n_rep,
+                   "roofline": {"bound": "hbm", "achieved": algo3 / (mean_ms / 1e3) / 1e9, "peak": HBM_PEAK_GBS,
+                                "unit": "GB/s", "frac": algo3 / (mean_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+                                "algorithmic_bytes": algo3,
+                                "kernel": "one launch = one replay of the captured validate call (mean of "
+                                          f"{n_rep} replays, HIP events on the replay stream)"}}
+        if not args.no_cpu:
+            thr = host_threads()
+            log(f"CPU oracle on the 4096-module batch, module-parallel on {thr} threads")
+            t_par, o3 = oracle_parallel(b3.words, b3.mod_off, thr)
+            o3a = np.stack([o3[k] for k in ("code", "sem_mask", "err_word", "n_inst")], axis=1).astype(np.uint32)
+            batched["cpu_oracle"] = {"value": W3 / t_par, "unit": "words/s", "cores": thr, "kind": "oracle",
+                                     "cpu_model": cpu_model(), "seconds": t_par,
+                                     "sample": f"the whole batch ({M3} modules, {W3} words), validate without "
+                                               f"index, module-parallel",
+                                     "results_match_gpu": bool(np.array_equal(o3a, g3res))}
 
-    records = records_leg(ctx, words, mod_off, idx_off, res, W) if args.records else None
-    rules = rules_leg(ctx, words, mod_off, ms_per_step) if args.module_rules else None
-    encode = encode_leg(ctx, dev) if args.encode else None
-    serving = serve_leg(args) if args.serve else None
+    records = records_leg(ctx, words, mod_off, idx_off, res, W) if not args.no_records else None
+    text = None
+    if not args.no_text:
+        log("text leg: disassembly of the timed module, options 11 and 0")
+        text = text_leg(ctx, words, mod_off, idx_off, res, W, n_inst)
+    rules = rules_leg(ctx, words, mod_off, ms_per_step) if not args.no_module_rules else None
+    encode = encode_leg(ctx, dev) if not args.no_encode else None
+    serving = serve_leg(args) if not args.no_serve else None
+    copy_gbps = copy_ceiling(dev)
+    log(f"plain device copy: {copy_gbps:.0f} GB/s")
 
     traffic = traffic_from_counters(W, n_inst)
     line = {
@@ -435,7 +580,9 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": timed_kernels,
                      "kernel_ms": 1e3 * k_avg_s,
-                     "algorithmic_bytes": algo_bytes},
+                     "algorithmic_bytes": algo_bytes,
+                     "copy_ceiling_GBps": copy_gbps,
+                     "frac_of_copy_ceiling": achieved / copy_gbps},
         "cpu_baseline": cpu,
         "hbm_fraction_whole_call": (value * (algo_bytes / W) / 1e9) / HBM_PEAK_GBS,
         "batched": batched,
@@ -443,6 +590,8 @@ def main():
     }
     if records is not None:
         line["records"] = records
+    if text is not None:
+        line["text"] = text
     if rules is not None:
         line["module_rules"] = rules
     if encode is not None:

@@ -416,11 +416,13 @@ int spv_decode_text(spv_ctx* ctx, const uint32_t* words, const int64_t* mod_off,
   p.mscan = reinterpret_cast<unsigned long long*>(base + L.mscan);
   p.mstate = reinterpret_cast<unsigned long long*>(base + L.mstate);
   p.lens = reinterpret_cast<uint32_t*>(base + L.lens);
+  p.lpos = reinterpret_cast<uint32_t*>(base + L.lpos);
   p.btot = reinterpret_cast<unsigned long long*>(base + L.btot);
   p.bstate = reinterpret_cast<unsigned long long*>(base + L.bstate);
   p.slots = reinterpret_cast<spv::TxtSlot*>(base + L.slots);
   p.slot_cap = L.slot_cap;
   p.nlist = reinterpret_cast<uint2*>(base + L.nlist);
+  p.bcount = reinterpret_cast<uint32_t*>(base + L.bcount);
   spv::launch_text(p, static_cast<hipStream_t>(stream));
   return check_launch(ctx);
 }

@@ -314,13 +314,12 @@ enum : uint32_t {
   kTxtGroup = 8u,
   kTxtNoHeader = 16u,
 };
-// Inline-name hash slot: key (module << 32 | target ID), the word position
-// of the module's first OpName of that target (atomicMin), and the length of
-// its name when usable (0 = print the number).
+// Inline-name hash slot: key (module << 32 | target ID) and, for the
+// module's first OpName of that target (atomicMin), its word position << 32 |
+// the length of its name when usable (0 = print the number).
 struct TxtSlot {
   unsigned long long key;
-  uint32_t pos;
-  uint32_t len;
+  unsigned long long pl;
 };
 constexpr unsigned long long kTxtEmpty = ~0ull;
 struct TParams {
@@ -339,14 +338,16 @@ struct TParams {
   unsigned long long* mscan;    // per module: header bytes << 29 | instructions, then the exclusive scan
   unsigned long long* mstate;   // look-back states of the module scan
   uint32_t* lens;               // per instruction: line bytes; after the scatter, offset in its block
+  uint32_t* lpos;               // per instruction: word position of its first word
   unsigned long long* btot;     // per block of 1024 instructions: bytes, then the exclusive scan
   unsigned long long* bstate;   // look-back states of the block scan
   TxtSlot* slots;               // inline-name hash (slot_cap slots, a power of two)
   int64_t slot_cap;
-  uint2* nlist;                 // OpName instructions: (module, word position)
+  uint2* nlist;                 // OpName instructions (module, word position), 1024 entries per block
+  uint32_t* bcount;             // OpName instructions per block of 1024 instructions
 };
 struct TLayout {
-  size_t ctrl, mscan, mstate, lens, btot, bstate, slots, nlist, total;
+  size_t ctrl, mscan, mstate, lens, lpos, btot, bstate, slots, nlist, bcount, total;
   int64_t slot_cap;
 };
 inline TLayout make_tlayout(int64_t n_modules, int64_t n_words, uint32_t options) {
@@ -360,6 +361,8 @@ inline TLayout make_tlayout(int64_t n_modules, int64_t n_words, uint32_t options
   off = align256(off + 128 * size_t((n_modules + 1) / 1024 + 2));
   L.lens = off;
   off = align256(off + 4 * size_t(n_words + 1));
+  L.lpos = off;
+  off = align256(off + 4 * size_t(n_words + 1));
   const int64_t nb = n_words / 1024 + 1;  // blocks of 1024 instructions, at most
   L.btot = off;
   off = align256(off + 8 * size_t(nb + 1));
@@ -372,8 +375,11 @@ inline TLayout make_tlayout(int64_t n_modules, int64_t n_words, uint32_t options
   L.slot_cap = (options & kTxtInlineNames) ? cap : 0;
   L.slots = off;
   off = align256(off + sizeof(TxtSlot) * size_t(L.slot_cap));
+  const bool names = (options & kTxtInlineNames) != 0;
   L.nlist = off;
-  off = align256(off + 8 * size_t(max_names));
+  off = align256(off + (names ? 8 * size_t(nb) * 1024 : 0));
+  L.bcount = off;
+  off = align256(off + (names ? 4 * size_t(nb) : 0));
   L.total = off;
   return L;
 }

@@ -27,8 +27,9 @@
 //
 // How: a scan over the modules gives each module's first instruction and
 // header bytes; with inline names, the OpName instructions are gathered into
-// a list and inserted into an open-addressing hash keyed by (module, ID),
-// where atomicMin keeps each ID's first OpName; a length pass sizes every
+// per-block regions of a list and inserted into an open-addressing hash keyed
+// by (module, ID), where a 64-bit atomicMin on (position, name length) keeps
+// each ID's first OpName; a length pass sizes every
 // line (the same line writer run into a counting sink) and totals blocks of
 // 1024 lines; a scan of those totals and an in-block scan in the scatter place
 // every line.  The scatter writes a slice of 256 lines into LDS at the byte
@@ -48,89 +49,82 @@ namespace {
 
 constexpr uint64_t kInstMask = (1ull << 29) - 1;  // low bits of the module scan: instructions
 constexpr int kHdrShift = 29;                      // high bits: header bytes
-constexpr int kStageBytes = 40960;                 // LDS staging per slice of 256 lines
+constexpr int kStageBytes = 30720;                 // LDS staging per slice of 256 lines
 
-// One opcode of the grammar: its name, the operand words before its string
-// (all operand words for an instruction without one), whether a string
-// follows, operand roles (2 bits per slot: 0 literal, 1 ID use, 2 result ID)
-// and literal kinds (3 bits per slot: 0 decimal, 1 capability, 2 addressing
-// model, 3 memory model, 4 execution model, 5 function control).
+// Every fixed token the lines print, concatenated: opcode names (ids 0..12),
+// capabilities 0..12, 22, 39 (13..27), addressing models 0..2 (28..30), memory
+// models 0..3 (31..34), execution models 0..6 (35..41), function control None,
+// Inline, DontInline, Pure, Const (42..46).  Enumerant names are those of the
+// SPIR-V specification.
+constexpr const char* kTokStr[] = {
+    "OpName", "OpMemoryModel", "OpEntryPoint", "OpCapability", "OpTypeInt", "OpConstant", "OpFunction",
+    "OpFunctionEnd", "OpLoad", "OpStore", "OpIAdd", "OpLabel", "OpReturn",
+    "Matrix", "Shader", "Geometry", "Tessellation", "Addresses", "Linkage", "Kernel", "Vector16",
+    "Float16Buffer", "Float16", "Float64", "Int64", "Int64Atomics", "Int16", "Int8",
+    "Logical", "Physical32", "Physical64",
+    "Simple", "GLSL450", "OpenCL", "Vulkan",
+    "Vertex", "TessellationControl", "TessellationEvaluation", "Geometry", "Fragment", "GLCompute", "Kernel",
+    "None", "Inline", "DontInline", "Pure", "Const"};
+constexpr int kNumTok = int(sizeof(kTokStr) / sizeof(kTokStr[0]));
+constexpr int kTokCap = 512;
+
+struct TokTable {
+  uint16_t off[kNumTok];
+  uint8_t len[kNumTok];
+  char chars[kTokCap];
+};
+
+constexpr TokTable make_tok_table() {
+  TokTable t{};
+  int o = 0;
+  for (int i = 0; i < kNumTok; ++i) {
+    int n = 0;
+    while (kTokStr[i][n]) ++n;
+    t.off[i] = uint16_t(o);
+    t.len[i] = uint8_t(n);
+    for (int k = 0; k < n; ++k) t.chars[o + k] = kTokStr[i][k];
+    o += n;
+  }
+  return t;
+}
+
+__constant__ TokTable kTok = make_tok_table();
+
+// One opcode of the grammar: its name's token, the operand words before its
+// string (all operand words for an instruction without one), whether a
+// string follows, operand roles (2 bits per slot: 0 literal, 1 ID use, 2
+// result ID) and literal kinds (3 bits per slot: 0 decimal, 1 capability, 2
+// addressing model, 3 memory model, 4 execution model, 5 function control).
 struct TxtOp {
-  const char* name;
-  uint32_t nfix, str, roles, lits;
+  uint32_t tok, nfix, str, roles, lits;
 };
 
 __device__ __forceinline__ TxtOp txt_op(uint32_t op) {
   switch (op) {
-    case 5: return {"OpName", 1, 1, 1u, 0u};
-    case 14: return {"OpMemoryModel", 2, 0, 0u, 2u | (3u << 3)};
-    case 15: return {"OpEntryPoint", 2, 1, 1u << 2, 4u};
-    case 17: return {"OpCapability", 1, 0, 0u, 1u};
-    case 21: return {"OpTypeInt", 3, 0, 2u, 0u};
-    case 43: return {"OpConstant", 3, 0, 1u | (2u << 2), 0u};
-    case 54: return {"OpFunction", 4, 0, 1u | (2u << 2) | (1u << 6), 5u << 6};
-    case 56: return {"OpFunctionEnd", 0, 0, 0u, 0u};
-    case 61: return {"OpLoad", 3, 0, 1u | (2u << 2) | (1u << 4), 0u};
-    case 62: return {"OpStore", 2, 0, 1u | (1u << 2), 0u};
-    case 128: return {"OpIAdd", 4, 0, 1u | (2u << 2) | (1u << 4) | (1u << 6), 0u};
-    case 248: return {"OpLabel", 1, 0, 2u, 0u};
-    default: return {"OpReturn", 0, 0, 0u, 0u};  // 253: decode admits no other opcode
+    case 5: return {0, 1, 1, 1u, 0u};
+    case 14: return {1, 2, 0, 0u, 2u | (3u << 3)};
+    case 15: return {2, 2, 1, 1u << 2, 4u};
+    case 17: return {3, 1, 0, 0u, 1u};
+    case 21: return {4, 3, 0, 2u, 0u};
+    case 43: return {5, 3, 0, 1u | (2u << 2), 0u};
+    case 54: return {6, 4, 0, 1u | (2u << 2) | (1u << 6), 5u << 6};
+    case 56: return {7, 0, 0, 0u, 0u};
+    case 61: return {8, 3, 0, 1u | (2u << 2) | (1u << 4), 0u};
+    case 62: return {9, 2, 0, 1u | (1u << 2), 0u};
+    case 128: return {10, 4, 0, 1u | (2u << 2) | (1u << 4) | (1u << 6), 0u};
+    case 248: return {11, 1, 0, 2u, 0u};
+    default: return {12, 0, 0, 0u, 0u};  // 253: decode admits no other opcode
   }
 }
 
-// Enumerant names of the SPIR-V specification; nullptr where the table has
-// no entry (the value prints in decimal).
-__device__ __forceinline__ const char* txt_enum(uint32_t kind, uint32_t v) {
-  if (kind == 1) {
-    switch (v) {
-      case 0: return "Matrix";
-      case 1: return "Shader";
-      case 2: return "Geometry";
-      case 3: return "Tessellation";
-      case 4: return "Addresses";
-      case 5: return "Linkage";
-      case 6: return "Kernel";
-      case 7: return "Vector16";
-      case 8: return "Float16Buffer";
-      case 9: return "Float16";
-      case 10: return "Float64";
-      case 11: return "Int64";
-      case 12: return "Int64Atomics";
-      case 22: return "Int16";
-      case 39: return "Int8";
-      default: return nullptr;
-    }
-  }
-  if (kind == 2) {
-    switch (v) {
-      case 0: return "Logical";
-      case 1: return "Physical32";
-      case 2: return "Physical64";
-      default: return nullptr;
-    }
-  }
-  if (kind == 3) {
-    switch (v) {
-      case 0: return "Simple";
-      case 1: return "GLSL450";
-      case 2: return "OpenCL";
-      case 3: return "Vulkan";
-      default: return nullptr;
-    }
-  }
-  if (kind == 4) {
-    switch (v) {
-      case 0: return "Vertex";
-      case 1: return "TessellationControl";
-      case 2: return "TessellationEvaluation";
-      case 3: return "Geometry";
-      case 4: return "Fragment";
-      case 5: return "GLCompute";
-      case 6: return "Kernel";
-      default: return nullptr;
-    }
-  }
-  return nullptr;
+// Token of enumerant v of literal kind 1..4, or -1 (the value prints in
+// decimal).
+__device__ __forceinline__ int txt_enum(uint32_t kind, uint32_t v) {
+  if (kind == 1) return v <= 12u ? 13 + int(v) : v == 22u ? 26 : v == 39u ? 27 : -1;
+  if (kind == 2) return v <= 2u ? 28 + int(v) : -1;
+  if (kind == 3) return v <= 3u ? 31 + int(v) : -1;
+  if (kind == 4) return v <= 6u ? 35 + int(v) : -1;
+  return -1;
 }
 
 // Output sinks of the line writer: a counter (lengths only), LDS staging, and
@@ -139,6 +133,7 @@ __device__ __forceinline__ const char* txt_enum(uint32_t kind, uint32_t v) {
 struct CountSink {
   static constexpr bool kWrite = false;
   uint32_t o;
+  const char* tok;
   __device__ __forceinline__ void put(uint32_t) { ++o; }
   __device__ __forceinline__ void put_at(uint32_t, uint32_t) {}
 };
@@ -146,6 +141,7 @@ struct LdsSink {
   static constexpr bool kWrite = true;
   uint8_t* p;
   uint32_t o;
+  const char* tok;  // the token characters, staged in LDS
   __device__ __forceinline__ void put(uint32_t c) { p[o++] = uint8_t(c); }
   __device__ __forceinline__ void put_at(uint32_t k, uint32_t c) { p[k] = uint8_t(c); }
 };
@@ -154,6 +150,7 @@ struct GlobalSink {
   uint8_t* p;
   int64_t g, cap;
   uint32_t o;
+  const char* tok;
   __device__ __forceinline__ void put(uint32_t c) {
     if (g + o < cap) p[g + o] = uint8_t(c);
     ++o;
@@ -164,12 +161,8 @@ struct GlobalSink {
 };
 
 __device__ __forceinline__ uint32_t ndigits(uint32_t v) {
-  uint32_t d = 1;
-  while (v >= 10u) {
-    v /= 10u;
-    ++d;
-  }
-  return d;
+  return v < 10u ? 1u : v < 100u ? 2u : v < 1000u ? 3u : v < 10000u ? 4u : v < 100000u ? 5u
+       : v < 1000000u ? 6u : v < 10000000u ? 7u : v < 100000000u ? 8u : v < 1000000000u ? 9u : 10u;
 }
 
 template <class S>
@@ -188,6 +181,17 @@ __device__ __forceinline__ void put_dec(S& s, uint32_t v) {
 template <class S>
 __device__ __forceinline__ void put_cstr(S& s, const char* c) {
   for (; *c; ++c) s.put(uint8_t(*c));
+}
+
+template <class S>
+__device__ __forceinline__ void put_tok(S& s, int id) {
+  const uint32_t n = kTok.len[id];
+  if constexpr (S::kWrite) {
+    const char* c = s.tok + kTok.off[id];
+    for (uint32_t k = 0; k < n; ++k) s.put(uint8_t(c[k]));
+  } else {
+    s.o += n;
+  }
 }
 
 template <class S>
@@ -236,7 +240,10 @@ __device__ __forceinline__ IdName txt_name(const TParams& P, unsigned long long 
   unsigned long long h = txt_mix(key) & (nslots - 1);
   while (true) {  // the table is at most half full, so an empty slot ends every probe
     const unsigned long long k = P.slots[h].key;
-    if (k == key) return IdName{P.slots[h].pos, P.slots[h].len};
+    if (k == key) {
+      const unsigned long long pl = P.slots[h].pl;
+      return IdName{uint32_t(pl >> 32), uint32_t(pl)};
+    }
     if (k == kTxtEmpty) return IdName{0u, 0u};
     h = (h + 1) & (nslots - 1);
   }
@@ -264,44 +271,71 @@ __device__ __forceinline__ void put_lit(S& s, bool hl, uint32_t kind, uint32_t v
   if (hl) color_on(s, '4');
   if (kind == 5) {  // function control: a bit mask
     if (v == 0) {
-      put_cstr(s, "None");
+      put_tok(s, 42);
     } else if (v & ~0xFu) {
       put_dec(s, v);
     } else {
       bool first = true;
-      for (uint32_t b = 0; b < 4; ++b) {
+      for (int b = 0; b < 4; ++b) {
         if (!(v & (1u << b))) continue;
         if (!first) s.put('|');
-        put_cstr(s, b == 0 ? "Inline" : b == 1 ? "DontInline" : b == 2 ? "Pure" : "Const");
+        put_tok(s, 43 + b);
         first = false;
       }
     }
   } else {
-    const char* e = txt_enum(kind, v);
-    if (e) put_cstr(s, e);
+    const int e = txt_enum(kind, v);
+    if (e >= 0) put_tok(s, e);
     else put_dec(s, v);
   }
   if (hl) color_off(s);
 }
 
-// A string literal (decode checked that it ends in a NUL within its last
-// word), quoted, with '"' and '\' escaped.
+// 0x80 in every byte of t that is zero, 0 elsewhere (exact per byte).
+__device__ __forceinline__ uint32_t zero_bytes(uint32_t t) {
+  return ~(((t & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | t | 0x7F7F7F7Fu);
+}
+
+// Bytes of the last word of a string before its NUL (decode checked that the
+// first NUL lies in the last word).
+__device__ __forceinline__ uint32_t last_word_bytes(uint32_t x) {
+  return uint32_t(__builtin_ctz(zero_bytes(x) | 0x80000000u)) >> 3;
+}
+
+// A string literal of nw words, quoted, with '"' and '\' escaped.  The
+// counter works on whole words: the length from the last word, the escapes by
+// byte compares.
 template <class S>
-__device__ __forceinline__ void put_string(S& s, const uint32_t* w) {
-  for (uint32_t i = 0;; ++i) {
-    const uint32_t x = w[i];
-    for (uint32_t q = 0; q < 4; ++q) {
-      const uint32_t c = (x >> (8 * q)) & 0xFFu;
-      if (c == 0) return;
-      if (c == '"' || c == '\\') s.put('\\');
-      s.put(c);
+__device__ __forceinline__ void put_string(S& s, const uint32_t* w, uint32_t nw) {
+  if constexpr (S::kWrite) {
+#pragma unroll 4
+    for (uint32_t i = 0; i < nw; ++i) {
+      const uint32_t x = w[i];
+      const uint32_t nb = i + 1 < nw ? 4u : last_word_bytes(x);
+      for (uint32_t q = 0; q < nb; ++q) {
+        const uint32_t c = (x >> (8 * q)) & 0xFFu;
+        if (c == '"' || c == '\\') s.put('\\');
+        s.put(c);
+      }
     }
+  } else {
+    uint32_t n = 0;
+#pragma unroll 4
+    for (uint32_t i = 0; i < nw; ++i) {
+      const uint32_t x = w[i];
+      const uint32_t nb = i + 1 < nw ? 4u : last_word_bytes(x);
+      const uint32_t live = nb == 4u ? 0x80808080u : (0x80808080u & ((1u << (8 * nb)) - 1u));
+      const uint32_t esc = zero_bytes(x ^ 0x22222222u) | zero_bytes(x ^ 0x5C5C5C5Cu);
+      n += nb + uint32_t(__builtin_popcount(esc & live));
+    }
+    s.o += n;
   }
 }
 
 // The text line of the instruction at word position pos of module m.
 template <class S>
-__device__ void txt_line(const TParams& P, unsigned long long nslots, uint32_t m, int64_t pos, S& s) {
+__device__ __forceinline__ void txt_line(const TParams& P, unsigned long long nslots, uint32_t m, int64_t pos,
+                                         S& s) {
   const uint32_t w0 = P.words[pos], op = w0 & 0xFFFFu;
   const TxtOp d = txt_op(op);
   const uint32_t opt = P.options;
@@ -331,7 +365,7 @@ __device__ void txt_line(const TParams& P, unsigned long long nslots, uint32_t m
     s.put(' ');
   }
   if (hl) color_on(s, '6');
-  put_cstr(s, d.name);
+  put_tok(s, int(d.tok));
   if (hl) color_off(s);
 #pragma unroll
   for (uint32_t k = 0; k < 4; ++k) {
@@ -350,7 +384,7 @@ __device__ void txt_line(const TParams& P, unsigned long long nslots, uint32_t m
     s.put(' ');
     if (hl) color_on(s, '2');
     s.put('"');
-    put_string(s, P.words + pos + 1 + d.nfix);
+    put_string(s, P.words + pos + 1 + d.nfix, (w0 >> 16) - 1 - d.nfix);
     s.put('"');
     if (hl) color_off(s);
   }
@@ -424,7 +458,7 @@ __global__ __launch_bounds__(kRecThreads) void k_txt_init(TParams P) {
     const bool hdr_ok = r.code == SPV_OK || (r.code >= SPV_E_BAD_WORD_COUNT && r.code <= SPV_E_MODULE_RULES);
     unsigned long long hb = 0;
     if (hdr_ok && !(P.options & kTxtNoHeader)) {
-      CountSink c{0};
+      CountSink c{0, nullptr};
       txt_header(P, m, c);
       hb = c.o;
     }
@@ -436,15 +470,19 @@ __global__ __launch_bounds__(kRecThreads) void k_txt_modscan(TParams P) {
   scan_block(P.mscan, P.M, P.mscan, P.mstate, &P.ctrl[0], &P.ctrl[2]);
 }
 
-// Inline names, step 1: the list of OpName instructions.
+// Inline names, step 1: the OpName instructions of every block of 1024
+// instructions, compacted into that block's own region of the list (no
+// shared counter), and their number.
 __global__ __launch_bounds__(kRecThreads) void k_txt_collect(TParams P) {
   __shared__ int64_t s_mb[2];
+  __shared__ uint32_t s_wc[kRecThreads / 64];
   if (P.ctrl[2]) return;
-  const int tid = threadIdx.x, lane = tid & 63;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t N = txt_count(P);
   const int64_t nb = (N + kScanBlock - 1) / kScanBlock;
   for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
     txt_bracket(P, b, N, s_mb);
+    uint32_t run = 0;  // names in the block's earlier slices
     for (int k = 0; k < kScanPerThread; ++k) {
       const int64_t r = b * kScanBlock + int64_t(k) * kRecThreads + tid;
       int64_t m = 0, pos = 0;
@@ -455,22 +493,45 @@ __global__ __launch_bounds__(kRecThreads) void k_txt_collect(TParams P) {
         is_name = (P.words[pos] & 0xFFFFu) == uint32_t(kOpName);
       }
       const uint64_t bal = __ballot(is_name);
-      if (bal) {
-        const int leader = __builtin_ctzll(bal);
-        uint32_t base = 0;
-        if (lane == leader) base = atomicAdd(&P.ctrl[3], uint32_t(__builtin_popcountll(bal)));
-        base = __shfl(base, leader);
-        if (is_name) {
-          const uint32_t rank = uint32_t(__builtin_popcountll(bal & ((1ull << lane) - 1ull)));
-          P.nlist[base + rank] = make_uint2(uint32_t(m), uint32_t(pos));
-        }
+      if (lane == 0) s_wc[wave] = uint32_t(__builtin_popcountll(bal));
+      __syncthreads();
+      uint32_t before = run, tot = 0;
+#pragma unroll
+      for (int w = 0; w < kRecThreads / 64; ++w) {
+        if (w < wave) before += s_wc[w];
+        tot += s_wc[w];
       }
+      if (is_name) {
+        const uint32_t rank = before + uint32_t(__builtin_popcountll(bal & ((1ull << lane) - 1ull)));
+        P.nlist[b * kScanBlock + rank] = make_uint2(uint32_t(m), uint32_t(pos));
+      }
+      run += tot;
+      __syncthreads();  // s_wc is rewritten by the next slice
     }
-    __syncthreads();  // s_mb is rewritten for the next block
+    if (tid == 0) P.bcount[b] = run;
   }
 }
 
-// Inline names, step 2: empty the slots in use.
+// Inline names, step 2: the number of OpName instructions (one block).
+__global__ __launch_bounds__(1024) void k_txt_ncount(TParams P) {
+  __shared__ uint32_t s_w[16];
+  if (P.ctrl[2]) return;
+  const int tid = threadIdx.x;
+  const int64_t nb = (txt_count(P) + kScanBlock - 1) / kScanBlock;
+  uint32_t sum = 0;
+  for (int64_t b = tid; b < nb; b += 1024) sum += P.bcount[b];
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) sum += __shfl_xor(sum, d);
+  if ((tid & 63) == 0) s_w[tid >> 6] = sum;
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t t = 0;
+    for (int w = 0; w < 16; ++w) t += s_w[w];
+    P.ctrl[3] = t;
+  }
+}
+
+// Inline names, step 3: empty the slots in use.
 __global__ __launch_bounds__(kRecThreads) void k_txt_hclear(TParams P) {
   if (P.ctrl[2]) return;
   const unsigned long long ns = txt_slots(P);
@@ -478,54 +539,49 @@ __global__ __launch_bounds__(kRecThreads) void k_txt_hclear(TParams P) {
   const unsigned long long nth = (unsigned long long)gridDim.x * blockDim.x;
   for (unsigned long long i = gtid; i < ns; i += nth) {
     P.slots[i].key = kTxtEmpty;
-    P.slots[i].pos = 0xFFFFFFFFu;
-    P.slots[i].len = 0u;
+    P.slots[i].pl = ~0ull;
   }
 }
 
-// Inline names, step 3: insert every OpName by (module, target); the slot
-// keeps the smallest word position, i.e. the module's first OpName.
+// Inline names, step 4: insert every OpName by (module, target) with its
+// name's length (0 when the name is not usable: empty, a character outside
+// [A-Za-z0-9_], or a leading digit); a 64-bit atomicMin on (word position <<
+// 32 | length) keeps the module's first OpName of each target.
 __global__ __launch_bounds__(kRecThreads) void k_txt_insert(TParams P) {
   if (P.ctrl[2]) return;
   const unsigned long long ns = txt_slots(P);
-  const uint32_t n = P.ctrl[3];
-  const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x, nth = gridDim.x * blockDim.x;
-  for (uint32_t i = gtid; i < n; i += nth) {
+  const int64_t n = ((txt_count(P) + kScanBlock - 1) / kScanBlock) * kScanBlock;
+  const int64_t gtid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x, nth = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t i = gtid; i < n; i += nth) {
+    if (uint32_t(i % kScanBlock) >= P.bcount[i / kScanBlock]) continue;
     const uint2 e = P.nlist[i];
+    const uint32_t nw = (P.words[e.y] >> 16) - 2;  // the name's words
+    const uint32_t* w = P.words + e.y + 2;
+    uint32_t len = 0;
+    bool ok = true;
+#pragma unroll 4
+    for (uint32_t k = 0; k < nw; ++k) {
+      const uint32_t x = w[k];
+      const uint32_t nb = k + 1 < nw ? 4u : last_word_bytes(x);
+      for (uint32_t q = 0; q < nb; ++q) {
+        const uint32_t c = (x >> (8 * q)) & 0xFFu;
+        const bool alpha = (c >= 'a' && c <= 'z') || (c >= 'A' && c <= 'Z') || c == '_';
+        const bool digit = c >= '0' && c <= '9';
+        if (!(alpha || (digit && (k | q) != 0))) ok = false;
+      }
+      len += nb;
+    }
+    const unsigned long long val = ((unsigned long long)e.y << 32) | (ok ? len : 0u);
     const unsigned long long key = ((unsigned long long)e.x << 32) | P.words[e.y + 1];
     unsigned long long h = txt_mix(key) & (ns - 1);
     while (true) {
       const unsigned long long prev = atomicCAS(&P.slots[h].key, kTxtEmpty, key);
       if (prev == kTxtEmpty || prev == key) {
-        atomicMin(&P.slots[h].pos, e.y);
+        atomicMin(&P.slots[h].pl, val);
         break;
       }
       h = (h + 1) & (ns - 1);
     }
-  }
-}
-
-// Inline names, step 4: the length of each kept name, 0 when it is not usable.
-__global__ __launch_bounds__(kRecThreads) void k_txt_nlen(TParams P) {
-  if (P.ctrl[2]) return;
-  const unsigned long long ns = txt_slots(P);
-  const unsigned long long gtid = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const unsigned long long nth = (unsigned long long)gridDim.x * blockDim.x;
-  for (unsigned long long i = gtid; i < ns; i += nth) {
-    if (P.slots[i].key == kTxtEmpty) continue;
-    const uint32_t* w = P.words + P.slots[i].pos + 2;
-    uint32_t len = 0;
-    bool ok = true;
-    for (uint32_t k = 0;; ++k) {
-      const uint32_t x = w[k >> 2];
-      const uint32_t c = (x >> (8 * (k & 3))) & 0xFFu;
-      if (c == 0) break;
-      const bool alpha = (c >= 'a' && c <= 'z') || (c >= 'A' && c <= 'Z') || c == '_';
-      const bool digit = c >= '0' && c <= '9';
-      if (!(alpha || (digit && k > 0))) ok = false;
-      ++len;
-    }
-    P.slots[i].len = (ok && len > 0) ? len : 0u;
   }
 }
 
@@ -545,9 +601,11 @@ __global__ __launch_bounds__(kRecThreads) void k_txt_lens(TParams P) {
       const int64_t r = b * kScanBlock + int64_t(k) * kRecThreads + tid;
       if (r < N) {
         const int64_t m = txt_module(P.mscan, s_mb[0], s_mb[1], r);
-        CountSink c{0};
-        txt_line(P, ns, uint32_t(m), txt_pos(P, m, r), c);
+        const int64_t pos = txt_pos(P, m, r);
+        CountSink c{0, nullptr};
+        txt_line(P, ns, uint32_t(m), pos, c);
         P.lens[r] = c.o;
+        P.lpos[r] = uint32_t(pos);
         sum += c.o;
       }
     }
@@ -580,8 +638,11 @@ __global__ __launch_bounds__(kRecThreads) void k_txt_scatter(TParams P) {
   __shared__ int64_t s_mb[2];
   __shared__ unsigned long long s_w[kRecThreads / 64];
   __shared__ long long s_g[2];
+  __shared__ char s_tok[kTokCap];
   if (P.ctrl[2]) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int i = tid; i < kTokCap; i += kRecThreads) s_tok[i] = kTok.chars[i];
+  __syncthreads();
   const int64_t N = txt_count(P);
   const int64_t nb = (N + kScanBlock - 1) / kScanBlock;
   const unsigned long long ns = (P.options & kTxtInlineNames) ? txt_slots(P) : 1;
@@ -625,11 +686,11 @@ __global__ __launch_bounds__(kRecThreads) void k_txt_scatter(TParams P) {
       const bool staged = G1 - G0a <= kStageBytes;
       if (valid) {
         if (staged) {
-          LdsSink sk{stage, uint32_t(g - G0a)};
-          txt_line(P, ns, uint32_t(m), txt_pos(P, m, r), sk);
+          LdsSink sk{stage, uint32_t(g - G0a), s_tok};
+          txt_line(P, ns, uint32_t(m), int64_t(P.lpos[r]), sk);
         } else {
-          GlobalSink sk{P.text, g, P.text_cap, 0u};
-          txt_line(P, ns, uint32_t(m), txt_pos(P, m, r), sk);
+          GlobalSink sk{P.text, g, P.text_cap, 0u, s_tok};
+          txt_line(P, ns, uint32_t(m), int64_t(P.lpos[r]), sk);
         }
       }
       __syncthreads();
@@ -670,7 +731,7 @@ __global__ __launch_bounds__(kRecThreads) void k_txt_modules(TParams P) {
     const int64_t off = int64_t(lx + (sm >> kHdrShift));
     P.text_mod_off[m] = off;
     if (m < P.M && (P.mscan[m + 1] >> kHdrShift) > (sm >> kHdrShift)) {
-      GlobalSink sk{P.text, off, P.text_cap, 0u};
+      GlobalSink sk{P.text, off, P.text_cap, 0u, nullptr};
       txt_header(P, m, sk);
     }
   }
@@ -687,9 +748,9 @@ void launch_text(const TParams& p, hipStream_t s) {
   hipLaunchKernelGGL(k_txt_modscan, dim3(int(p.M / kScanBlock + 1)), dim3(kRecThreads), 0, s, p);
   if (p.options & kTxtInlineNames) {
     hipLaunchKernelGGL(k_txt_collect, dim3(gb), dim3(kRecThreads), 0, s, p);
+    hipLaunchKernelGGL(k_txt_ncount, dim3(1), dim3(1024), 0, s, p);
     hipLaunchKernelGGL(k_txt_hclear, dim3(grid(p.slot_cap)), dim3(kRecThreads), 0, s, p);
-    hipLaunchKernelGGL(k_txt_insert, dim3(grid(p.cap_inst / 3 + 1)), dim3(kRecThreads), 0, s, p);
-    hipLaunchKernelGGL(k_txt_nlen, dim3(grid(p.slot_cap)), dim3(kRecThreads), 0, s, p);
+    hipLaunchKernelGGL(k_txt_insert, dim3(grid(p.cap_inst)), dim3(kRecThreads), 0, s, p);
   }
   hipLaunchKernelGGL(k_txt_lens, dim3(gb), dim3(kRecThreads), 0, s, p);
   hipLaunchKernelGGL(k_txt_bscan, dim3(int(nb / kScanBlock + 1)), dim3(kRecThreads), 0, s, p);
