@@ -79,9 +79,23 @@ extern "C" {
  * 64 no OpEntryPoint. */
 #define SPV_E_MODULE_RULES 11
 
-/* spv_validate option: hold modules that pass every check to the
- * module-level rules (SPV_E_MODULE_RULES).  Needs the instruction index. */
-#define SPV_OPT_MODULE_RULES 1u
+/* spv_validate options (option_flags, a bit set):
+ *   SPV_OPT_NO_SEMANTIC  stop after the parse stage: the call is spv_decode
+ *                        (section "Parsing Operand Kinds"); cannot be combined
+ *                        with SPV_OPT_MODULE_RULES (SPV_ERR_INVALID_ARG);
+ *   SPV_OPT_MODULE_RULES hold modules that pass every check to the
+ *                        module-level rules of section "Validation Rules"
+ *                        (SPV_E_MODULE_RULES);
+ *   SPV_OPT_DEBUG_CHECKS before anything else, a device check of mod_off:
+ *                        mod_off[0] == 0, non-decreasing, every module below
+ *                        2^32 words, mod_off[n_modules] == n_words.  On a
+ *                        violation nothing else runs and the call returns
+ *                        SPV_ERR_INVALID_ARG.  The check reads its status word
+ *                        back, so the call synchronises its stream, and under
+ *                        stream capture it returns SPV_ERR_INVALID_ARG. */
+#define SPV_OPT_NO_SEMANTIC 1u
+#define SPV_OPT_MODULE_RULES 2u
+#define SPV_OPT_DEBUG_CHECKS 4u
 
 /* ---- encode status codes (per module) ---------------------------------- */
 #define SPV_ENC_OK 0
@@ -142,7 +156,11 @@ int spv_get_tuning(spv_ctx *ctx, int *blocks_per_cu, int *encode_block);
  * and may be reused by later calls on the same stream. */
 int spv_workspace_size(spv_ctx *ctx, int64_t n_modules, int64_t n_words, size_t *bytes);
 
-/* Decode: header and parse stages; results[m] for every module, and, when
+/* Decode: the header and parse stages of the validator (section "Validation
+ * Rules": the library checks a module before it stores it), reading the
+ * binary as the disassembler does (section "Dis/Assembler") with the header
+ * fields of section "SPIR-V Library" and the operand word counts of section
+ * "Parsing Operand Kinds".  results[m] for every module, and, when
  * idx_off / idx_op are non-NULL, the instruction index in gapped CSR form:
  * module m's instruction j is idx_off[mod_off[m] + j] (word offset of its
  * first word within the module) and idx_op[mod_off[m] + j] (opcode), for
@@ -157,10 +175,11 @@ int spv_decode(spv_ctx *ctx, const uint32_t *words, const int64_t *mod_off, int6
                uint32_t *idx_off, uint16_t *idx_op, int64_t idx_cap, spv_result *results, void *ws,
                size_t ws_bytes, void *stream);
 
-/* Validate: decode plus the semantic stage (bound, define-once, undefined
- * IDs).  Same arguments as spv_decode, plus option_flags: 0, or
- * SPV_OPT_MODULE_RULES to add the module-level rules of section "Validation
- * Rules" as a last stage (SPV_ERR_INVALID_ARG for other bits). */
+/* Validate: decode plus the semantic stage: every ID below the header's
+ * bound (section "SPIR-V Library", bound paragraph), each result ID defined
+ * once and every used ID defined somewhere in the module (the SSA rule of
+ * section "Enabling Function Composition").  Same arguments as spv_decode,
+ * plus option_flags, a set of SPV_OPT_* bits (SPV_ERR_INVALID_ARG for others). */
 int spv_validate(spv_ctx *ctx, const uint32_t *words, const int64_t *mod_off, int64_t n_modules, int64_t n_words,
                  uint32_t *idx_off, uint16_t *idx_op, int64_t idx_cap, spv_result *results, uint32_t option_flags,
                  void *ws, size_t ws_bytes, void *stream);

@@ -8,9 +8,20 @@
 // slot can ever hold (n > cap_words - 1) is rejected when it reaches the
 // front of the queue; the first request that fits no more ends the batch and
 // waits for the next free slot.
+//
+// A batch ends in one of two ways: its launch failed (a copy, the validate
+// call or the graph could not be issued), or the worker saw its completion
+// event.  Either way complete_batch turns every request of the batch into a
+// completion record at once: status 0 with the module's result when the batch
+// ran, else the error status with a zero result; the slot is free again.
 #pragma once
 
 #include <stdint.h>
+#include <string.h>
+
+#include <vector>
+
+#include "../../include/spvgpu.h"
 
 namespace spv {
 
@@ -46,6 +57,25 @@ inline int64_t bucket_up(int64_t x) {
   const int lg = 63 - __builtin_clzll(uint64_t(x));
   const int64_t step = int64_t(1) << (lg - 3);
   return (x + step - 1) / step * step;
+}
+
+// Completion records of a finished batch.  req_at(i) gives the i-th request
+// of the batch (fields id and t_arr_ns); res is the batch's result array, or
+// nullptr when status != 0 (results are then zero).
+template <class ReqAt>
+inline void complete_batch(int64_t n, ReqAt req_at, const spv_result* res, int status, int64_t t_done_ns,
+                           std::vector<spv_completion>& out) {
+  for (int64_t i = 0; i < n; ++i) {
+    spv_completion c;
+    memset(&c, 0, sizeof(c));
+    c.id = req_at(i).id;
+    if (status == 0 && res) c.result = res[i];
+    c.status = status;
+    c.t_arrival_ns = req_at(i).t_arr_ns;
+    c.t_done_ns = t_done_ns;
+    c.batch_modules = n;
+    out.push_back(c);
+  }
 }
 
 }  // namespace spv

@@ -8,6 +8,7 @@
 #include <utility>
 #include <vector>
 
+#include "spv_checks.h"
 #include "spv_internal.h"
 
 // Scratch of spv_validate_noalloc: one copy per GPU, held until the process
@@ -92,9 +93,46 @@ int check_launch(spv_ctx* ctx) {
   return SPV_SUCCESS;
 }
 
+// Option bits of spv_validate: the three known ones, the rules only with the
+// semantic stage.
+bool flags_ok(uint32_t f) {
+  if (f & ~(SPV_OPT_NO_SEMANTIC | SPV_OPT_MODULE_RULES | SPV_OPT_DEBUG_CHECKS)) return false;
+  return !((f & SPV_OPT_NO_SEMANTIC) && (f & SPV_OPT_MODULE_RULES));
+}
+
+// SPV_OPT_DEBUG_CHECKS: the device check of the module offsets.  status[0]
+// collects a violation bit; a single block clears it first.
+__global__ void k_dbg_clear(uint32_t* status) { status[0] = 0; }
+
+__global__ __launch_bounds__(256) void k_dbg_offsets(const int64_t* mod_off, int64_t M, int64_t W,
+                                                      uint32_t* status) {
+  const int64_t gtid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t nth = int64_t(gridDim.x) * blockDim.x;
+  bool bad = false;
+  if (gtid == 0) bad = !spv::offsets_ends_ok(mod_off[0], mod_off[M], W);
+  for (int64_t i = gtid; i < M; i += nth) bad |= !spv::offsets_pair_ok(mod_off[i], mod_off[i + 1]);
+  if (bad) atomicOr(status, 1u);
+}
+
+// Runs the offset check and reads its verdict (synchronises the stream).
+int debug_check_offsets(spv_ctx* ctx, const int64_t* mod_off, int64_t M, int64_t W, uint32_t* status,
+                        hipStream_t s) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess) return fail_hip(ctx, hipGetLastError());
+  if (cs != hipStreamCaptureStatusNone) return SPV_ERR_INVALID_ARG;  // a read-back cannot be captured
+  hipLaunchKernelGGL(k_dbg_clear, dim3(1), dim3(1), 0, s, status);
+  const int64_t g = M / 256 + 1;
+  hipLaunchKernelGGL(k_dbg_offsets, dim3(int(g > 4096 ? 4096 : g)), dim3(256), 0, s, mod_off, M, W, status);
+  uint32_t h = 0;
+  hipError_t e = hipMemcpyAsync(&h, status, sizeof(h), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail_hip(ctx, e);
+  return h ? SPV_ERR_INVALID_ARG : SPV_SUCCESS;
+}
+
 int run_validate(spv_ctx* ctx, const uint32_t* words, const int64_t* mod_off, int64_t n_modules, int64_t n_words,
                  uint32_t* idx_off, uint16_t* idx_op, int64_t idx_cap, spv_result* results, int semantic, void* ws,
-                 size_t ws_bytes, void* stream, bool allow_timing = true, bool rules = false) {
+                 size_t ws_bytes, void* stream, bool allow_timing = true, bool rules = false, bool debug = false) {
   if (!ctx) return SPV_ERR_INVALID_ARG;
   if (n_modules < 0 || n_words < 0) return SPV_ERR_INVALID_ARG;
   if (n_modules >= (int64_t(1) << 31) - 1) return SPV_ERR_LIMIT;
@@ -109,6 +147,12 @@ int run_validate(spv_ctx* ctx, const uint32_t* words, const int64_t* mod_off, in
   DeviceGuard g(ctx->device);
   if (!g.ok) return fail_hip(ctx, hipErrorInvalidDevice);
   char* base = static_cast<char*>(ws);
+  if (debug) {
+    const int rc = debug_check_offsets(ctx, mod_off, n_modules, n_words,
+                                       reinterpret_cast<uint32_t*>(base + L.ctrl) + spv::kCtlDebug,
+                                       static_cast<hipStream_t>(stream));
+    if (rc != SPV_SUCCESS) return rc;
+  }
   spv::VParams p;
   p.words = words;
   p.mod_off = mod_off;
@@ -309,23 +353,24 @@ int spv_decode(spv_ctx* ctx, const uint32_t* words, const int64_t* mod_off, int6
 int spv_validate(spv_ctx* ctx, const uint32_t* words, const int64_t* mod_off, int64_t n_modules, int64_t n_words,
                  uint32_t* idx_off, uint16_t* idx_op, int64_t idx_cap, spv_result* results, uint32_t option_flags,
                  void* ws, size_t ws_bytes, void* stream) {
-  if ((option_flags & ~SPV_OPT_MODULE_RULES) != 0) return SPV_ERR_INVALID_ARG;
-  const bool rules = (option_flags & SPV_OPT_MODULE_RULES) != 0;
-  return run_validate(ctx, words, mod_off, n_modules, n_words, idx_off, idx_op, idx_cap, results, 1, ws, ws_bytes,
-                      stream, true, rules);
+  if (!flags_ok(option_flags)) return SPV_ERR_INVALID_ARG;
+  return run_validate(ctx, words, mod_off, n_modules, n_words, idx_off, idx_op, idx_cap, results,
+                      (option_flags & SPV_OPT_NO_SEMANTIC) ? 0 : 1, ws, ws_bytes, stream, true,
+                      (option_flags & SPV_OPT_MODULE_RULES) != 0, (option_flags & SPV_OPT_DEBUG_CHECKS) != 0);
 }
 
 int spv_validate_noalloc(spv_ctx* ctx, const uint32_t* words, const int64_t* mod_off, int64_t n_modules,
                          int64_t n_words, uint32_t* idx_off, uint16_t* idx_op, int64_t idx_cap, spv_result* results,
                          uint32_t option_flags, void* stream) {
   if (!ctx || n_modules < 0 || n_words < 0) return SPV_ERR_INVALID_ARG;
-  if ((option_flags & ~SPV_OPT_MODULE_RULES) != 0) return SPV_ERR_INVALID_ARG;
+  if (!flags_ok(option_flags)) return SPV_ERR_INVALID_ARG;
   if (spv::make_layout(n_modules, n_words).total > size_t(SPV_NOALLOC_SCRATCH_BYTES)) return SPV_ERR_WORKSPACE;
   if (ctx->scratch == nullptr) return fail_hip(ctx, hipErrorInvalidSymbol);
-  const bool rules = (option_flags & SPV_OPT_MODULE_RULES) != 0;
   // no event recording on this path (nothing is created or allocated)
-  return run_validate(ctx, words, mod_off, n_modules, n_words, idx_off, idx_op, idx_cap, results, 1, ctx->scratch,
-                      size_t(SPV_NOALLOC_SCRATCH_BYTES), stream, false, rules);
+  return run_validate(ctx, words, mod_off, n_modules, n_words, idx_off, idx_op, idx_cap, results,
+                      (option_flags & SPV_OPT_NO_SEMANTIC) ? 0 : 1, ctx->scratch, size_t(SPV_NOALLOC_SCRATCH_BYTES),
+                      stream, false, (option_flags & SPV_OPT_MODULE_RULES) != 0,
+                      (option_flags & SPV_OPT_DEBUG_CHECKS) != 0);
 }
 
 int spv_encode_bound(int64_t n_modules, int64_t n_records, int64_t n_opnd_words, int64_t n_string_records,

@@ -130,7 +130,8 @@ enum {
   kCtlMode = 4,
   kCtlClaimR = 5,
   kCtlDoneR = 6,
-  kCtlP2Tiles = 7  // entries of the second pass's tile list
+  kCtlP2Tiles = 7,  // entries of the second pass's tile list
+  kCtlDebug = 15    // status word of the SPV_OPT_DEBUG_CHECKS offset check
 };
 // kCtlMode: kModeResolved when the chain and resolve passes settled every
 // tile's entry and count prefix (the main pass then walks without look-back);

@@ -114,14 +114,16 @@ hipError_t launch_batch(spv_server* S, Slot& sl, int64_t M, int64_t W) {
     auto key = std::make_pair(Mp, Wp);
     auto it = sl.graphs.find(key);
     if (it == sl.graphs.end()) {
-      hipGraph_t g;
+      hipGraph_t g = nullptr;
       e = hipStreamBeginCapture(sl.stream, hipStreamCaptureModeThreadLocal);
       if (e != hipSuccess) return e;
       int r = spv_validate(S->ctx, sl.d_words, sl.d_mod_off, Mp, Wp, sl.d_idx_off, sl.d_idx_op, Wp, sl.d_res, 0,
                            sl.d_ws, sl.ws_bytes, sl.stream);
-      e = hipStreamEndCapture(sl.stream, &g);
-      if (r != SPV_SUCCESS) return hipErrorLaunchFailure;
-      if (e != hipSuccess) return e;
+      e = hipStreamEndCapture(sl.stream, &g);  // (ends the capture on every path)
+      if (r != SPV_SUCCESS || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return e != hipSuccess ? e : hipErrorLaunchFailure;
+      }
       hipGraphExec_t ge;
       e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
       (void)hipGraphDestroy(g);
@@ -134,6 +136,19 @@ hipError_t launch_batch(spv_server* S, Slot& sl, int64_t M, int64_t W) {
   e = hipMemcpyAsync(sl.h_res, sl.d_res, size_t(M) * sizeof(spv_result), hipMemcpyDeviceToHost, sl.stream);
   if (e == hipSuccess) e = hipEventRecord(sl.done, sl.stream);
   return e;
+}
+
+// Complete every request of the slot's batch (status 0: with the results the
+// batch copied back) and free the slot.
+void finish_batch(spv_server* S, Slot& sl, int status) {
+  const int64_t t_done = now_ns(S);
+  std::lock_guard<std::mutex> lk(S->mu);
+  spv::complete_batch(
+      int64_t(sl.batch.size()), [&](int64_t i) -> const Req& { return sl.batch[size_t(i)]; },
+      status == 0 ? sl.h_res : nullptr, status, t_done, S->completed);
+  S->in_flight -= int64_t(sl.batch.size());
+  sl.batch.clear();
+  sl.busy = false;
 }
 
 void worker_main(spv_server* S) {
@@ -192,21 +207,7 @@ void worker_main(spv_server* S) {
       hipError_t q = hipEventQuery(sl.done);
       if (q == hipErrorNotReady) continue;
       if (q != hipSuccess) S->err = q;
-      const int64_t t_done = now_ns(S);
-      std::lock_guard<std::mutex> lk(S->mu);
-      for (size_t i = 0; i < sl.batch.size(); ++i) {
-        spv_completion c;
-        c.id = sl.batch[i].id;
-        c.result = sl.h_res[i];
-        c.status = (q == hipSuccess) ? 0 : SPV_ERR_HIP;
-        c.t_arrival_ns = sl.batch[i].t_arr_ns;
-        c.t_done_ns = t_done;
-        c.batch_modules = int64_t(sl.batch.size());
-        S->completed.push_back(c);
-      }
-      S->in_flight -= int64_t(sl.batch.size());
-      sl.batch.clear();
-      sl.busy = false;
+      finish_batch(S, sl, q == hipSuccess ? 0 : SPV_ERR_HIP);
       did = true;
     }
     // admission: fill every free slot with arrived requests that fit
@@ -242,8 +243,14 @@ void worker_main(spv_server* S) {
       }
       if (M == 0) continue;
       hipError_t e = launch_batch(S, sl, M, W);
-      if (e != hipSuccess) S->err = e;
-      sl.busy = true;
+      if (e != hipSuccess) {
+        // nothing of this batch will complete on the GPU: its requests end
+        // now with SPV_ERR_HIP and the slot stays free
+        S->err = e;
+        finish_batch(S, sl, SPV_ERR_HIP);
+      } else {
+        sl.busy = true;
+      }
       S->n_batches += 1;
       S->n_modules += M;
       S->n_words += W;

@@ -1,6 +1,7 @@
-"""Host-side serving logic (no GPU): the server's admission rules and graph
-size buckets (paper_2305_09493_amd/csrc/spv_admission.h), built with g++
-through a small C shim and checked against the rules stated in the test."""
+"""Host-side serving logic (no GPU): the server's admission rules, graph
+size buckets and batch completion records
+(paper_2305_09493_amd/csrc/spv_admission.h), built with g++ through a small C
+shim and checked against the rules stated in the test."""
 import ctypes
 import os
 import shutil
@@ -21,6 +22,17 @@ extern "C" int64_t admit(int64_t n, const int64_t* sizes, int64_t max_batch, int
   return spv::admit_batch(n, [&](int64_t i) { return sizes[i]; }, max_batch, cap_modules, cap_words, action);
 }
 extern "C" int64_t bucket(int64_t x) { return spv::bucket_up(x); }
+struct R { int64_t id, t_arr_ns; };
+// a batch of n requests whose launch failed (res == nullptr) or ran
+extern "C" int64_t complete(int64_t n, const int64_t* ids, const int64_t* t_arr, const spv_result* res, int status,
+                            int64_t t_done, spv_completion* out) {
+  std::vector<R> batch;
+  for (int64_t i = 0; i < n; ++i) batch.push_back(R{ids[i], t_arr[i]});
+  std::vector<spv_completion> done;
+  spv::complete_batch(n, [&](int64_t i) -> const R& { return batch[size_t(i)]; }, res, status, t_done, done);
+  for (size_t i = 0; i < done.size(); ++i) out[i] = done[i];
+  return int64_t(done.size());
+}
 """
 
 
@@ -39,6 +51,9 @@ def lib():
                           ctypes.c_void_p]
     lib.bucket.restype = ctypes.c_int64
     lib.bucket.argtypes = [ctypes.c_int64]
+    lib.complete.restype = ctypes.c_int64
+    lib.complete.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                             ctypes.c_int64, ctypes.c_void_p]
     yield lib
     shutil.rmtree(d, ignore_errors=True)
 
@@ -105,3 +120,47 @@ def test_graph_buckets_pad_little(lib):
     # a few buckets per power of two
     assert all(lib.bucket(lib.bucket(x)) == lib.bucket(x) for x in range(1, 3000))
     assert len([b for b in seen if 1 << 20 <= b < 1 << 21]) <= 8
+
+
+COMPLETION = np.dtype([("id", "<i8"), ("code", "<u4"), ("sem_mask", "<u4"), ("err_word", "<u4"), ("n_inst", "<u4"),
+                       ("status", "<i4"), ("pad", "<i4"), ("t_arrival_ns", "<i8"), ("t_done_ns", "<i8"),
+                       ("batch_modules", "<i8")])
+
+
+def _complete(lib, ids, t_arr, res, status, t_done):
+    ids = np.ascontiguousarray(ids, np.int64)
+    t_arr = np.ascontiguousarray(t_arr, np.int64)
+    out = np.zeros(max(ids.size, 1), COMPLETION)
+    rp = None if res is None else np.ascontiguousarray(res, np.uint32).ctypes.data
+    n = lib.complete(ids.size, ids.ctypes.data, t_arr.ctypes.data, rp, status, t_done, out.ctypes.data)
+    return out[:n]
+
+
+def test_completion_layout_matches_the_header():
+    """The record layout the test reads (spv_completion in include/spvgpu.h)."""
+    import re
+    hdr = open(os.path.join(ROOT, "include", "spvgpu.h")).read()
+    body = hdr[hdr.index("typedef struct {", hdr.index("spv_completion") - 600):hdr.index("} spv_completion;")]
+    fields = re.findall(r"(\w+)\s+(\w+)(?:\[\d+\])?;", body)
+    assert [f for _, f in fields][:3] == ["id", "result", "status"]
+
+
+def test_failed_launch_completes_every_request_with_the_error(lib):
+    """A batch whose launch failed ends at once: every request gets the error
+    status and a zero result (never a stale result of an earlier batch)."""
+    ids, t_arr = [11, 12, 13], [100, 200, 300]
+    out = _complete(lib, ids, t_arr, None, -4, 999)
+    assert list(out["id"]) == ids and list(out["t_arrival_ns"]) == t_arr
+    assert all(out["status"] == -4) and all(out["t_done_ns"] == 999) and all(out["batch_modules"] == 3)
+    for k in ("code", "sem_mask", "err_word", "n_inst"):
+        assert all(out[k] == 0)
+
+
+def test_completed_batch_carries_its_results(lib):
+    res = np.array([[0, 0, 0xFFFFFFFF, 7], [10, 4, 0xFFFFFFFF, 9]], np.uint32)
+    out = _complete(lib, [5, 6], [1, 2], res, 0, 50)
+    assert list(out["status"]) == [0, 0]
+    assert list(out["code"]) == [0, 10] and list(out["n_inst"]) == [7, 9] and list(out["sem_mask"]) == [0, 4]
+    # a completion that failed on the GPU keeps no result either
+    out = _complete(lib, [5, 6], [1, 2], res, -4, 50)
+    assert all(out["status"] == -4) and all(out["code"] == 0) and all(out["n_inst"] == 0)
