@@ -181,9 +181,13 @@ struct LEnt {
 constexpr uint32_t kInfoEnd = 8u, kInfoHdrOk = 16u, kInfoSparse = 32u;
 constexpr int kWinWords = 128;  // LDS window of 8192 result IDs per tile
 constexpr int kTwTail = 32;     // words past the tile end kept in LDS
+// LDS index of tile position q: one pad word after every 16, so that the 64
+// lanes of a wave, 16 words apart, read a position each from distinct banks
+__device__ __forceinline__ int twx(int q) { return q + (q >> 4); }
+constexpr int kTwSize = (kTileWords + kTwTail) + (kTileWords + kTwTail) / 16 + 1;
 
 struct Shared {
-  uint32_t tw[kTileWords + kTwTail] __attribute__((aligned(16)));  // the tile's words (+ the next 32)
+  uint32_t tw[kTwSize] __attribute__((aligned(16)));  // the tile's words (+ the next 32), padded (twx)
   uint32_t stage[kTileWords];  // staged index entries: tile position | opcode << 16
   uint32_t tbl[257];
   LEnt list[kListMax];
@@ -221,7 +225,7 @@ struct Shared {
 // its strings lane by lane), so that five blocks fit on a CU.
 constexpr int kNameCap = 1024;
 struct WalkShared {
-  uint32_t tw[kTileWords + kTwTail] __attribute__((aligned(16)));
+  uint32_t tw[kTwSize] __attribute__((aligned(16)));
   uint16_t names[kNameCap];
   uint32_t tbl[257];
   LEnt list[kListMax];
@@ -1271,11 +1275,16 @@ __device__ __forceinline__ void main_body(SH& S, const VParams& P) {
   const int tid = threadIdx.x;
   const int wave = tid >> 6;
   const int lane = tid & 63;
-  // LDS copy of the tile's words, row-major, then the next tile's first
-  // words.  (A column-major copy, whose per-position reads hit distinct
-  // banks, measured slower in the resolved walk: 199 against 183 us.)
-  auto twx = [](int q) -> int { return q; };
-  auto tw_store4 = [&](int l, int i, const uint4& v) { *reinterpret_cast<uint4*>(&S.tw[l * kLaneWords + 4 * i]) = v; };
+  // LDS copy of the tile's words, then the next tile's first words, with a
+  // pad word after every 16 (twx).  (A column-major copy measured slower in
+  // the resolved walk, 199 against 183 us: its 16-byte stores conflict.)
+  auto tw_store4 = [&](int l, int i, const uint4& v) {
+    const int q = twx(l * kLaneWords + 4 * i);
+    S.tw[q] = v.x;
+    S.tw[q + 1] = v.y;
+    S.tw[q + 2] = v.z;
+    S.tw[q + 3] = v.w;
+  };
   // the first tile is claimed here, each later one near the end of the tile
   // before it
   if (tid == 0)
@@ -1378,7 +1387,7 @@ __device__ __forceinline__ void main_body(SH& S, const VParams& P) {
         S.tw[twx(tid * kLaneWords + i)] = L.w[i];
       }
     }
-    if (tid < kTwTail) S.tw[kTileWords + tid] = (pf_tile == t) ? pf_tail : ((t1 + tid < P.W) ? P.words[t1 + tid] : 0u);
+    if (tid < kTwTail) S.tw[twx(kTileWords + tid)] = (pf_tile == t) ? pf_tail : ((t1 + tid < P.W) ? P.words[t1 + tid] : 0u);
     if (wave == 0) build_list(S, P, t, t0, t1);
     if (tid < kListMax) {
       S.modflags[tid] = 0;
@@ -1917,7 +1926,7 @@ __device__ __forceinline__ void main_body(SH& S, const VParams& P) {
           int jm = lane_mod_at(L, 15);
           const LEnt& le = S.list[jm];
           if (!(le.info & kInfoHdrOk)) continue;
-          const uint32_t v = S.tw[kTileWords + k];
+          const uint32_t v = S.tw[twx(kTileWords + k)];
           const int wj = win_of(jm);
           const uint32_t base = wj >= 0 ? win_base(wj) : 0u;
           if (d && wj >= 0 && v != 0u && v < le.bound && v >= base && v - base < 64u * wsz) {
@@ -2029,7 +2038,8 @@ __device__ __forceinline__ void main_body(SH& S, const VParams& P) {
       }
     }
 
-    if constexpr (kRes) issue_prefetch();
+    // (the resolved walk does not prefetch: the registers cost more occupancy
+    // than the early loads gain)
 
     // ---- module ends owned by this lane: positions 1..16 of the window
     {
@@ -2093,7 +2103,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_main(VParams P) {
 }
 
 template <bool kSem, bool kIdx, bool kRules>
-__global__ __launch_bounds__(kBlock, 5) void k_walk(VParams P) {
+__global__ __launch_bounds__(kBlock, 6) void k_walk(VParams P) {
   __shared__ WalkShared S;
   if (P.ctrl[kCtlMode] != kModeResolved) return;  // the single-pass walk runs next
   main_body<kSem, kIdx, true, WalkShared, kRules>(S, P);
