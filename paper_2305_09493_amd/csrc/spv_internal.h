@@ -22,7 +22,8 @@ constexpr int kWaves = SPV_TILE_WAVES;            // waves per tile block
 constexpr int kBlock = 64 * kWaves;               // threads per tile block
 constexpr int kTileWords = kLaneWords * kBlock;   // words per tile
 constexpr int kListMax = 64;                      // module starts per tile window (fast path)
-constexpr int kMaxSpanTiles = 17;                 // a 65535-word instruction spans <= 17 tiles
+constexpr int kMaxSpanTiles = (65535 + kTileWords - 1) / kTileWords + 1;  // tiles a 65535-word instruction spans
+static_assert(kMaxSpanTiles <= 64, "the entry look-back reads one tile per lane of a wave");
 
 // 4-bit exit codes of a lane transfer function: 0..13 exit offset into the
 // next lane, kFar = exit not representable (long instruction), kDead = the

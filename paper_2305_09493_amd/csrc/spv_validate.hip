@@ -1010,7 +1010,7 @@ struct ChainShared {
 
 // (6 waves per SIMD: the pass has little shared state, so more resident
 // blocks hide the load latency of each tile)
-__global__ __launch_bounds__(kBlock, 6) void k_chain(VParams P) {
+__global__ __launch_bounds__(kBlock, 24 / kWaves) void k_chain(VParams P) {
   __shared__ ChainShared S;
   if (threadIdx.x == 0) S.cache_ok = 0;
   init_table(S.tbl);
@@ -2096,14 +2096,14 @@ __device__ __forceinline__ void main_body(SH& S, const VParams& P) {
 }
 
 template <bool kSem, bool kIdx>
-__global__ __launch_bounds__(kBlock, 4) void k_main(VParams P) {
+__global__ __launch_bounds__(kBlock, 16 / kWaves) void k_main(VParams P) {
   __shared__ Shared S;
   if (P.ctrl[kCtlMode] == kModeResolved) return;  // the resolved walk ran
   main_body<kSem, kIdx, false>(S, P);
 }
 
 template <bool kSem, bool kIdx, bool kRules>
-__global__ __launch_bounds__(kBlock, 6) void k_walk(VParams P) {
+__global__ __launch_bounds__(kBlock, 24 / kWaves) void k_walk(VParams P) {
   __shared__ WalkShared S;
   if (P.ctrl[kCtlMode] != kModeResolved) return;  // the single-pass walk runs next
   main_body<kSem, kIdx, true, WalkShared, kRules>(S, P);
