@@ -69,12 +69,16 @@ def _contig(a, dtype):
     return np.ascontiguousarray(np.asarray(a, dtype=dtype))
 
 
-def validate(words, mod_off, semantic: bool = True, index: bool = True, rules: bool = False):
+def validate(words, mod_off, semantic: bool = True, index: bool = True, rules: bool = False, offsets: bool = False,
+             before_use: bool = False):
     """Per-module results (structured array) and, if index, the gapped-CSR
     instruction index (idx_off uint32[W], idx_op uint16[W]; entries past each
     module's n_inst are left 0).  With semantic and rules, modules that pass
     every check are held to the module-level rules (section "Validation
-    Rules"; code E_MODULE_RULES)."""
+    Rules"; code E_MODULE_RULES).  before_use counts an ID used before any
+    instruction defines it as undefined (OpName targets and OpEntryPoint
+    functions may name later definitions); offsets puts the word offset of
+    the first instruction of the primary semantic class in err_word."""
     lib = _load()
     words = _contig(words, np.uint32)
     mod_off = _contig(mod_off, np.int64)
@@ -82,7 +86,8 @@ def validate(words, mod_off, semantic: bool = True, index: bool = True, rules: b
     res = np.zeros(m, dtype=RESULT_DTYPE)
     idx_off = np.zeros(words.size, np.uint32) if index else None
     idx_op = np.zeros(words.size, np.uint16) if index else None
-    rc = lib.oracle_validate(_ptr(words), _ptr(mod_off), m, int(bool(semantic)), int(bool(rules)),
+    opts = (1 if rules else 0) | (2 if offsets else 0) | (4 if before_use else 0)
+    rc = lib.oracle_validate(_ptr(words), _ptr(mod_off), m, int(bool(semantic)), opts,
                              _ptr(idx_off) if index else None, _ptr(idx_op) if index else None, _ptr(res))
     if rc != 0:
         raise RuntimeError("oracle_validate failed")

@@ -158,13 +158,92 @@ static uint32_t missing_rules(const uint32_t *w, uint64_t n) {
   return (capability ? 0u : 8u) | (memory_model ? 0u : 16u) | (function ? 0u : 32u) | (entry_point ? 0u : 64u);
 }
 
+/* Options of the semantic stage (bits of `opts`). */
+enum { ORC_OPT_RULES = 1, ORC_OPT_OFFSETS = 2, ORC_OPT_BEFORE_USE = 4 };
+
+/* An ID use that may name an ID defined later in the module: the target of
+ * OpName and the function of OpEntryPoint (debug and mode-setting operands,
+ * which SPIR-V places before the definitions they name). */
+static int forward_use_ok(uint32_t op, uint32_t slot) { return (op == 5 && slot == 0) || (op == 15 && slot == 1); }
+
+typedef struct {
+  uint32_t v, pos;
+} orc_def;
+
+static int cmp_def(const void *a, const void *b) {
+  const orc_def *x = (const orc_def *)a, *y = (const orc_def *)b;
+  if (x->v != y->v) return (x->v > y->v) - (x->v < y->v);
+  return (x->pos > y->pos) - (x->pos < y->pos);
+}
+
+/* Word offset of the first definition of v, or 0xFFFFFFFF if none (defs
+ * sorted by ID, then position). */
+static uint32_t first_def(const orc_def *d, uint64_t n, uint32_t v) {
+  uint64_t lo = 0, hi = n;
+  while (lo < hi) {
+    uint64_t mid = lo + (hi - lo) / 2;
+    if (d[mid].v < v) lo = mid + 1;
+    else hi = mid;
+  }
+  return (lo < n && d[lo].v == v) ? d[lo].pos : 0xFFFFFFFFu;
+}
+
+/* Semantic-stage positions of a module that passed the parse stage: the word
+ * offset of the first instruction (module order) with an ID operand out of
+ * bound, of the first whose in-bound result ID an earlier instruction already
+ * defines, and of the first with an in-bound ID use that no instruction
+ * defines, or, with before_use, that no earlier instruction defines (OpName
+ * targets and OpEntryPoint functions may name later definitions).
+ * 0xFFFFFFFF where there is none.  Returns 0, or -1 without memory. */
+static int semantic_positions(const uint32_t *w, uint64_t n, uint32_t bound, int before_use, uint32_t *f_oob,
+                              uint32_t *f_dup, uint32_t *f_undef) {
+  orc_def *defs = (orc_def *)malloc((n + 1) * sizeof(orc_def));
+  if (!defs) return -1;
+  uint64_t nd = 0;
+  *f_oob = *f_dup = *f_undef = 0xFFFFFFFFu;
+  for (uint64_t p = 5; p < n; p += w[p] >> 16) {
+    const orc_inst *g = lookup(w[p] & 0xFFFFu);
+    for (uint32_t s = 0; g->roles[s] != '\0' && g->roles[s] != 'S'; ++s) {
+      char role = g->roles[s];
+      if (role != 'U' && role != 'D') continue;
+      uint32_t v = w[p + 1 + s];
+      if (v == 0 || v >= bound) {
+        if (*f_oob == 0xFFFFFFFFu) *f_oob = (uint32_t)p;
+      } else if (role == 'D') {
+        defs[nd].v = v;
+        defs[nd].pos = (uint32_t)p;
+        ++nd;
+      }
+    }
+  }
+  qsort(defs, nd, sizeof(orc_def), cmp_def);
+  for (uint64_t i = 1; i < nd; ++i) /* the second definition of an ID */
+    if (defs[i].v == defs[i - 1].v && defs[i].pos < *f_dup) *f_dup = defs[i].pos;
+  for (uint64_t p = 5; p < n && *f_undef == 0xFFFFFFFFu; p += w[p] >> 16) {
+    uint32_t op = w[p] & 0xFFFFu;
+    const orc_inst *g = lookup(op);
+    for (uint32_t s = 0; g->roles[s] != '\0' && g->roles[s] != 'S'; ++s) {
+      uint32_t v = w[p + 1 + s];
+      if (g->roles[s] != 'U' || v == 0 || v >= bound) continue;
+      uint32_t d = first_def(defs, nd, v);
+      if (d == 0xFFFFFFFFu || (before_use && !forward_use_ok(op, s) && d >= p)) *f_undef = (uint32_t)p;
+    }
+  }
+  free(defs);
+  return 0;
+}
+
 /* Decode (and, if semantic != 0, validate) one module w[0..n).  Instruction
  * j of the valid prefix goes to idx_off[j] / idx_op[j] when they are given.
- * With semantic and rules, a module that passes every check is then held to
- * the module-level rules.
- * Returns 0, or -1 if memory for the semantic stage could not be had. */
-static int check_module(const uint32_t *w, uint64_t n, int semantic, int rules, uint32_t *idx_off, uint16_t *idx_op,
+ * Options of the semantic stage (opts): ORC_OPT_BEFORE_USE counts a use
+ * whose ID only a later instruction defines as undefined (the forward
+ * operands of forward_use_ok aside); ORC_OPT_OFFSETS puts in err_word the
+ * word offset of the first instruction of the primary semantic class;
+ * ORC_OPT_RULES holds a module that passes every check to the module-level
+ * rules.  Returns 0, or -1 if memory for the semantic stage could not be had. */
+static int check_module(const uint32_t *w, uint64_t n, int semantic, int opts, uint32_t *idx_off, uint16_t *idx_op,
                         orc_result *r) {
+  const int rules = (opts & ORC_OPT_RULES) != 0;
   r->code = ORC_OK;
   r->sem_mask = 0;
   r->err_word = 0xFFFFFFFFu;
@@ -256,10 +335,20 @@ static int check_module(const uint32_t *w, uint64_t n, int semantic, int rules, 
     if (!contains(defs, nd, uses[i])) undef = 1;
   free(defs);
   free(uses);
+  uint32_t f_oob = 0xFFFFFFFFu, f_dup = 0xFFFFFFFFu, f_undef = 0xFFFFFFFFu;
+  if (opts & (ORC_OPT_OFFSETS | ORC_OPT_BEFORE_USE)) {
+    if (semantic_positions(w, n, bound, (opts & ORC_OPT_BEFORE_USE) != 0, &f_oob, &f_dup, &f_undef) != 0) return -1;
+    if (opts & ORC_OPT_BEFORE_USE) undef = f_undef != 0xFFFFFFFFu;
+  }
   r->sem_mask = (oob ? 1u : 0u) | (dup ? 2u : 0u) | (undef ? 4u : 0u);
   if (oob) r->code = ORC_ID_OUT_OF_BOUND;
   else if (dup) r->code = ORC_DUPLICATE_ID;
   else if (undef) r->code = ORC_UNDEFINED_ID;
+  if (opts & ORC_OPT_OFFSETS) {
+    if (r->code == ORC_ID_OUT_OF_BOUND) r->err_word = f_oob;
+    else if (r->code == ORC_DUPLICATE_ID) r->err_word = f_dup;
+    else if (r->code == ORC_UNDEFINED_ID) r->err_word = f_undef;
+  }
   if (rules && r->code == ORC_OK) {
     r->sem_mask = missing_rules(w, n);
     if (r->sem_mask) r->code = ORC_MODULE_RULES;
@@ -271,12 +360,12 @@ static int check_module(const uint32_t *w, uint64_t n, int semantic, int rules, 
  * words[mod_off[m] .. mod_off[m+1]).  Index arrays, when given, are gapped
  * CSR: module m's instruction j is at idx_off[mod_off[m] + j] (a word offset
  * within the module) and idx_op[mod_off[m] + j].  Returns 0 or -1. */
-int oracle_validate(const uint32_t *words, const int64_t *mod_off, int64_t n_modules, int semantic, int rules,
+int oracle_validate(const uint32_t *words, const int64_t *mod_off, int64_t n_modules, int semantic, int opts,
                     uint32_t *idx_off, uint16_t *idx_op, orc_result *results) {
   for (int64_t m = 0; m < n_modules; ++m) {
     int64_t b = mod_off[m], e = mod_off[m + 1];
     if (e < b) return -1;
-    if (check_module(words + b, (uint64_t)(e - b), semantic, rules, idx_off ? idx_off + b : NULL,
+    if (check_module(words + b, (uint64_t)(e - b), semantic, opts, idx_off ? idx_off + b : NULL,
                      idx_op ? idx_op + b : NULL, &results[m]) != 0)
       return -1;
   }

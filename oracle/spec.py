@@ -49,8 +49,17 @@ def _string_words_ok(raw: bytes) -> bool:
 RULES = {8: {17}, 16: {14}, 32: {54}, 64: {15}}   # capability, memory model, function, entry point
 
 
-def check(words, semantic: bool = True, rules: bool = False):
-    """(code, sem_mask, err_word, n_inst, [(offset, opcode), ...])."""
+# ID uses that may name a later definition: OpName's target, OpEntryPoint's
+# function (opcode, operand slot)
+FORWARD_USES = {(5, 0), (15, 1)}
+
+
+def check(words, semantic: bool = True, rules: bool = False, offsets: bool = False, before_use: bool = False):
+    """(code, sem_mask, err_word, n_inst, [(offset, opcode), ...]).
+
+    before_use: a use counts as undefined unless an earlier instruction
+    defines its ID (FORWARD_USES aside); offsets: err_word of a semantic
+    failure is the offset of the first instruction of the primary class."""
     w = [int(x) & 0xFFFFFFFF for x in words]
     n = len(w)
     raw = struct.pack("<%dI" % n, *w)
@@ -102,13 +111,41 @@ def check(words, semantic: bool = True, rules: bool = False):
                 used.add(v)
     dup = any(c > 1 for c in defined.values())
     undef = bool(used - set(defined))
+    # the same walk again, in module order, for the first offenders: an
+    # instruction is the first of its class when no earlier one is
+    seen = set()
+    first = {}
+    for pos, opcode in insts:
+        for slot, kind in enumerate(KINDS[opcode]):
+            if kind not in ("id", "result"):
+                continue
+            v = w[pos + 1 + slot]
+            if not (0 < v < bound):
+                first.setdefault("oob", pos)
+            elif kind == "result":
+                if v in seen:
+                    first.setdefault("dup", pos)
+        for slot, kind in enumerate(KINDS[opcode]):
+            v = w[pos + 1 + slot] if kind != "str" else None
+            if kind == "id" and 0 < v < bound:
+                late = before_use and (opcode, slot) not in FORWARD_USES and v not in seen
+                if v not in defined or late:
+                    first.setdefault("undef", pos)
+        for slot, kind in enumerate(KINDS[opcode]):
+            if kind == "result":
+                seen.add(w[pos + 1 + slot])
+    if before_use:
+        undef = "undef" in first
     mask = (1 if out_of_bound else 0) | (2 if dup else 0) | (4 if undef else 0)
     code = 8 if out_of_bound else 9 if dup else 10 if undef else 0
+    err = 0xFFFFFFFF
+    if offsets and code:
+        err = first[{8: "oob", 9: "dup", 10: "undef"}[code]]
     if rules and code == 0:
         present = Counter(opcode for _, opcode in insts)
         mask = sum(bit for bit, ops in RULES.items() if not any(present[o] for o in ops))
         code = 11 if mask else 0
-    return (code, mask, 0xFFFFFFFF, len(insts), insts)
+    return (code, mask, err, len(insts), insts)
 
 
 def encode_module(records, version_word=0x00010600, generator_word=0):

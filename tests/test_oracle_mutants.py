@@ -24,8 +24,9 @@ MUTANTS = [
     ("minor version limit", "|| minor > 6)", "|| minor > 7)"),
     ("schema not checked", "if (w[4] != 0) {", "if (0) {"),
     ("duplicate ignored", "if (defs[i] == defs[i - 1]) dup = 1;", ";"),
-    ("ID 0 allowed", "if (v == 0 || v >= bound) {", "if (v >= bound) {"),
-    ("bound inclusive", "if (v == 0 || v >= bound) {", "if (v == 0 || v > bound) {"),
+    ("ID 0 allowed", "if (v == 0 || v >= bound) {\n        oob = 1;", "if (v >= bound) {\n        oob = 1;"),
+    ("bound inclusive", "if (v == 0 || v >= bound) {\n        oob = 1;", "if (v == 0 || v > bound) {\n        oob = 1;"),
+    ("position pass: ID 0 allowed", "if (v == 0 || v >= bound) {\n        if (*f_oob", "if (v >= bound) {\n        if (*f_oob"),
     ("priority DUP over OOB", "if (oob) r->code = ORC_ID_OUT_OF_BOUND;\n  else if (dup)",
      "if (dup) r->code = ORC_DUPLICATE_ID;\n  else if (oob)"),
     ("NUL anywhere accepted", "if (first_nul / 4 != n_words - 1) return 0;", ";"),
@@ -54,6 +55,14 @@ MUTANTS = [
     ("encode little-endian swapped", "word |= byte << (8 * b);", "word |= byte << (8 * (3 - b));"),
     ("encode failed module keeps its header", "    if (code != ORC_ENC_OK) {\n      word_mod_off[m + 1] = out;",
      "    if (code != ORC_ENC_OK) {\n      word_mod_off[m + 1] = out + 5;"),
+    ("first duplicate taken as the first definition",
+     "if (defs[i].v == defs[i - 1].v && defs[i].pos < *f_dup) *f_dup = defs[i].pos;",
+     "if (defs[i].v == defs[i - 1].v && defs[i].pos < *f_dup) *f_dup = defs[i - 1].pos;"),
+    ("a use at its own definition counts as defined", "!forward_use_ok(op, s) && d >= p)", "!forward_use_ok(op, s) && d > p)"),
+    ("no forward uses allowed", "(before_use && !forward_use_ok(op, s) && d >= p)", "(before_use && d >= p)"),
+    ("offset of the wrong class", "if (r->code == ORC_ID_OUT_OF_BOUND) r->err_word = f_oob;",
+     "if (r->code == ORC_ID_OUT_OF_BOUND) r->err_word = f_dup;"),
+    ("defined-before-use ignored", "if (opts & ORC_OPT_BEFORE_USE) undef = f_undef != 0xFFFFFFFFu;", ";"),
     ("text: opcode column 14", "for (int64_t c = width; c < 15; ++c)", "for (int64_t c = width; c < 14; ++c)"),
     ("text: last OpName wins", "if (k == 0 || names[k - 1].id != names[i].id) names[k++] = names[i];",
      "if (k > 0 && names[k - 1].id == names[i].id) names[k - 1] = names[i];\n        else names[k++] = names[i];"),
@@ -107,6 +116,10 @@ def _battery():
     for case in dis.CASES:
         checks.append((f"text {case['name']}", lambda c=case: dis.test_golden_disassembly(c)))
     checks.append(("text random", dis.test_random_tiny_modules_agree_with_second_statement))
+    import test_oracle_positions as posn
+    for case in posn.CASES:
+        checks.append((f"positions {case[0]}", lambda c=case: posn.test_hand_written_positions(*c)))
+    checks.append(("positions and rules", posn.test_rules_follow_the_before_use_stage))
     checks.append(("text batch", dis.test_batch_offsets_and_truncation))
     for name, fn in checks:
         try:
