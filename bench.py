@@ -100,7 +100,7 @@ def copy_calibration():
     log(f"copy calibration: {n * 4} bytes per copy, 3 copies")
 
 
-def encode_leg(ctx, dev, steps=10):
+def encode_leg(ctx, dev, steps=10, cpu=True):
     """Encode 10M records split into 1024 modules; records/s and output words/s
     (graph replays of one captured call; the eager time per call too)."""
     import torch
@@ -141,10 +141,19 @@ def encode_leg(ctx, dev, steps=10):
     words_out = int(out[1][-1].item())
     expect = int(sum(m.words.size for m in mods))
     bytes_moved = (2 * N + 4 * (N + 1) + 4 * r["opnd"].size + 4 * (N + 1) + r["chars"].size) + 4 * words_out
-    return {"records": N, "modules": M, "ms_per_call": 1e3 * dt, "ms_per_call_eager": 1e3 * dt_eager,
-            "records_per_s": N / dt,
-            "words_out_per_s": words_out / dt, "algorithmic_GBps": bytes_moved / dt / 1e9,
-            "hbm_frac": bytes_moved / dt / 1e9 / HBM_PEAK_GBS, "output_matches_generator": words_out == expect}
+    leg = {"records": N, "modules": M, "ms_per_call": 1e3 * dt, "ms_per_call_eager": 1e3 * dt_eager,
+           "records_per_s": N / dt,
+           "words_out_per_s": words_out / dt, "algorithmic_GBps": bytes_moved / dt / 1e9,
+           "hbm_frac": bytes_moved / dt / 1e9 / HBM_PEAK_GBS, "output_matches_generator": words_out == expect}
+    if cpu:
+        thr = host_threads()
+        log(f"CPU oracle encode of the same records, module-parallel on {thr} threads")
+        t_par, n_par = oracle_encode_parallel(r, thr)
+        leg["cpu_oracle"] = {"value": N / t_par, "unit": "records/s", "cores": thr, "kind": "oracle",
+                             "cpu_model": cpu_model(), "seconds": t_par,
+                             "sample": f"all {N} records in {M} modules, module-parallel",
+                             "words_match_gpu": n_par == words_out}
+    return leg
 
 
 def records_leg(ctx, words, mod_off, idx_off, res, W, steps=10):
@@ -221,6 +230,33 @@ def text_leg(ctx, words, mod_off, idx_off, res, W, n_inst, options_list=(11, 0),
         del graph, text
         torch.cuda.empty_cache()
     return out
+
+
+def oracle_encode_parallel(r, threads):
+    """The oracle's encoder over a record batch, module-parallel (contiguous
+    groups of modules of about equal records, one per host thread).  Returns
+    (seconds, words written)."""
+    import concurrent.futures as cf
+
+    import oracle
+    rmo = r["rec_mod_off"]
+    M = rmo.size - 1
+    cuts = np.unique(np.searchsorted(rmo, np.linspace(0, rmo[-1], threads + 1)).clip(0, M))
+    cuts[0], cuts[-1] = 0, M
+
+    def run(a, b):
+        r0, r1 = int(rmo[a]), int(rmo[b])
+        oo = r["opnd_off"][r0:r1 + 1]
+        so = r["str_off"][r0:r1 + 1]
+        w, _, _, _ = oracle.encode(r["op"][r0:r1], oo - oo[0], r["opnd"][oo[0]:oo[-1]], so - so[0],
+                                   r["chars"][so[0]:so[-1]], rmo[a:b + 1] - r0)
+        return w.size
+
+    oracle.encode_bound(1, 1, 1, 1)  # build / load outside the timing
+    t = time.perf_counter()
+    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        n = sum(ex.map(lambda ab: run(*ab), zip(cuts[:-1], cuts[1:])))
+    return time.perf_counter() - t, n
 
 
 def copy_ceiling(dev, n_bytes=1 << 30, steps=10):
@@ -366,7 +402,7 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=3.0, help="measured seconds per rate")
     ap.add_argument("--serve-warmup", type=float, default=1.0,
                     help="seconds of arrivals served before the measured ones and left out of p50/p99")
-    ap.add_argument("--serve-pool", type=int, default=2048)
+    ap.add_argument("--serve-pool", type=int, default=8192)
     args = ap.parse_args()
     if args.only_main:
         args.no_cpu = args.no_batched = args.no_encode = args.no_records = args.no_text = True
@@ -554,7 +590,7 @@ def main():
         log("text leg: disassembly of the timed module, options 11 and 0")
         text = text_leg(ctx, words, mod_off, idx_off, res, W, n_inst)
     rules = rules_leg(ctx, words, mod_off, ms_per_step) if not args.no_module_rules else None
-    encode = encode_leg(ctx, dev) if not args.no_encode else None
+    encode = encode_leg(ctx, dev, cpu=not args.no_cpu) if not args.no_encode else None
     serving = serve_leg(args) if not args.no_serve else None
     copy_gbps = copy_ceiling(dev)
     log(f"plain device copy: {copy_gbps:.0f} GB/s")

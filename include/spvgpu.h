@@ -82,7 +82,8 @@ extern "C" {
 /* spv_validate options (option_flags, a bit set):
  *   SPV_OPT_NO_SEMANTIC  stop after the parse stage: the call is spv_decode
  *                        (section "Parsing Operand Kinds"); cannot be combined
- *                        with SPV_OPT_MODULE_RULES (SPV_ERR_INVALID_ARG);
+ *                        with the options of the semantic stage below
+ *                        (SPV_ERR_INVALID_ARG);
  *   SPV_OPT_MODULE_RULES hold modules that pass every check to the
  *                        module-level rules of section "Validation Rules"
  *                        (SPV_E_MODULE_RULES);
@@ -92,10 +93,26 @@ extern "C" {
  *                        violation nothing else runs and the call returns
  *                        SPV_ERR_INVALID_ARG.  The check reads its status word
  *                        back, so the call synchronises its stream, and under
- *                        stream capture it returns SPV_ERR_INVALID_ARG. */
+ *                        stream capture it returns SPV_ERR_INVALID_ARG;
+ *   SPV_OPT_SEM_OFFSETS  a module that fails the semantic stage gets in
+ *                        err_word the word offset (within the module) of the
+ *                        first instruction, in module order, that breaks
+ *                        the rule of its primary code: an ID operand out of
+ *                        bound, a result ID that an earlier instruction
+ *                        already defines, a used ID that is not defined;
+ *   SPV_OPT_DEF_BEFORE_USE the stricter reading of the SSA rule of section
+ *                        "Enabling Function Composition": a used ID must be
+ *                        defined by an earlier instruction (OpName targets
+ *                        and OpEntryPoint functions may still name later
+ *                        definitions); other uses are SPV_E_UNDEFINED_ID.
+ * The last two run extra kernels after the call's results are written; they
+ * need the instruction index (idx_off / idx_op, else SPV_ERR_INVALID_ARG)
+ * and reuse the workspace's ID sets. */
 #define SPV_OPT_NO_SEMANTIC 1u
 #define SPV_OPT_MODULE_RULES 2u
 #define SPV_OPT_DEBUG_CHECKS 4u
+#define SPV_OPT_SEM_OFFSETS 8u
+#define SPV_OPT_DEF_BEFORE_USE 16u
 
 /* ---- encode status codes (per module) ---------------------------------- */
 #define SPV_ENC_OK 0

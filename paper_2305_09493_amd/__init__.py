@@ -27,7 +27,7 @@ OK, E_TRUNCATED_HEADER, E_BAD_MAGIC, E_BAD_VERSION, E_BAD_SCHEMA = 0, 1, 2, 3, 4
 E_BAD_WORD_COUNT, E_UNKNOWN_OPCODE, E_BAD_STRING = 5, 6, 7
 E_ID_OUT_OF_BOUND, E_DUPLICATE_ID, E_UNDEFINED_ID = 8, 9, 10
 E_MODULE_RULES = 11  # validate(module_rules=True): sem_mask = 8 no capability | 16 no memory model | 32 no function | 64 no entry point
-OPT_NO_SEMANTIC, OPT_MODULE_RULES, OPT_DEBUG_CHECKS = 1, 2, 4  # spv_validate option bits
+OPT_NO_SEMANTIC, OPT_MODULE_RULES, OPT_DEBUG_CHECKS, OPT_SEM_OFFSETS, OPT_DEF_BEFORE_USE = 1, 2, 4, 8, 16  # spv_validate option bits
 E_SPIN_LIMIT = 0xDEAD  # every result of a call whose inter-block wait gave up (repeat the call)
 ENC_OK, ENC_UNKNOWN_OPCODE, ENC_OPERAND_COUNT, ENC_BAD_STRING, ENC_TOO_LONG, ENC_BAD_ID, ENC_CAPACITY = range(7)
 
@@ -223,14 +223,19 @@ def _run(semantic: bool, words, mod_off, index: bool, ctx: Optional[Context], st
 
 
 def validate(words, mod_off, index: bool = True, ctx: Optional[Context] = None, stream=None, out=None,
-             workspace=None, module_rules: bool = False, debug_checks: bool = False):
+             workspace=None, module_rules: bool = False, debug_checks: bool = False, sem_offsets: bool = False,
+             def_before_use: bool = False):
     """Per-module results int32[M, 4] (code, sem_mask, err_word, n_inst) and,
     if index, the gapped-CSR instruction index (idx_off int32[W], idx_op
     int16[W]).  module_rules adds the module-level rules as a last stage
     (E_MODULE_RULES); debug_checks first checks mod_off on the device (the
-    call then synchronises its stream, and a bad mod_off raises SpvError)."""
-    return _run(True, words, mod_off, index, ctx, stream, out, workspace,
-                (OPT_MODULE_RULES if module_rules else 0) | (OPT_DEBUG_CHECKS if debug_checks else 0))
+    call then synchronises its stream, and a bad mod_off raises SpvError);
+    sem_offsets puts the offset of the first instruction of the primary
+    semantic failure in err_word; def_before_use needs every used ID defined
+    by an earlier instruction (both need the index)."""
+    flags = ((OPT_MODULE_RULES if module_rules else 0) | (OPT_DEBUG_CHECKS if debug_checks else 0) |
+             (OPT_SEM_OFFSETS if sem_offsets else 0) | (OPT_DEF_BEFORE_USE if def_before_use else 0))
+    return _run(True, words, mod_off, index, ctx, stream, out, workspace, flags)
 
 
 NOALLOC_SCRATCH_BYTES = 64 << 20  # SPV_NOALLOC_SCRATCH_BYTES

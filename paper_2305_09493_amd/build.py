@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libspvgpu.so")
-SOURCES = ["spv_api.hip", "spv_validate.hip", "spv_encode.hip", "spv_records.hip", "spv_text.hip", "spv_server.hip"]
+SOURCES = ["spv_api.hip", "spv_validate.hip", "spv_encode.hip", "spv_records.hip", "spv_text.hip", "spv_diag.hip", "spv_server.hip"]
 ARCH = os.environ.get("SPVGPU_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

@@ -96,8 +96,10 @@ int check_launch(spv_ctx* ctx) {
 // Option bits of spv_validate: the three known ones, the rules only with the
 // semantic stage.
 bool flags_ok(uint32_t f) {
-  if (f & ~(SPV_OPT_NO_SEMANTIC | SPV_OPT_MODULE_RULES | SPV_OPT_DEBUG_CHECKS)) return false;
-  return !((f & SPV_OPT_NO_SEMANTIC) && (f & SPV_OPT_MODULE_RULES));
+  if (f & ~(SPV_OPT_NO_SEMANTIC | SPV_OPT_MODULE_RULES | SPV_OPT_DEBUG_CHECKS | SPV_OPT_SEM_OFFSETS |
+            SPV_OPT_DEF_BEFORE_USE))
+    return false;
+  return !((f & SPV_OPT_NO_SEMANTIC) && (f & (SPV_OPT_MODULE_RULES | SPV_OPT_SEM_OFFSETS | SPV_OPT_DEF_BEFORE_USE)));
 }
 
 // SPV_OPT_DEBUG_CHECKS: the device check of the module offsets.  status[0]
@@ -132,7 +134,8 @@ int debug_check_offsets(spv_ctx* ctx, const int64_t* mod_off, int64_t M, int64_t
 
 int run_validate(spv_ctx* ctx, const uint32_t* words, const int64_t* mod_off, int64_t n_modules, int64_t n_words,
                  uint32_t* idx_off, uint16_t* idx_op, int64_t idx_cap, spv_result* results, int semantic, void* ws,
-                 size_t ws_bytes, void* stream, bool allow_timing = true, bool rules = false, bool debug = false) {
+                 size_t ws_bytes, void* stream, bool allow_timing = true, bool rules = false, bool debug = false,
+                 uint32_t diag_flags = 0) {
   if (!ctx) return SPV_ERR_INVALID_ARG;
   if (n_modules < 0 || n_words < 0) return SPV_ERR_INVALID_ARG;
   if (n_modules >= (int64_t(1) << 31) - 1) return SPV_ERR_LIMIT;
@@ -142,6 +145,7 @@ int run_validate(spv_ctx* ctx, const uint32_t* words, const int64_t* mod_off, in
   bool index = idx_off != nullptr || idx_op != nullptr;
   if (index && (!idx_off || !idx_op)) return SPV_ERR_INVALID_ARG;
   if (index && idx_cap < n_words) return SPV_ERR_CAPACITY;
+  if (diag_flags && !index) return SPV_ERR_INVALID_ARG;  // the positions are found through the index
   spv::Layout L = spv::make_layout(n_modules, n_words);
   if (!ws || ws_bytes < L.total) return SPV_ERR_WORKSPACE;
   DeviceGuard g(ctx->device);
@@ -179,6 +183,9 @@ int run_validate(spv_ctx* ctx, const uint32_t* words, const int64_t* mod_off, in
   // small batches: the second pass decides its own work (no phase-1 launch)
   p.p1_inline = (semantic && n_modules <= 256 && p.n_tiles > 0) ? 1 : 0;
   p.rules = rules ? 1 : 0;
+  p.diag = reinterpret_cast<uint4*>(base + L.diag);
+  p.sem_offsets = (diag_flags & SPV_OPT_SEM_OFFSETS) ? 1 : 0;
+  p.before_use = (diag_flags & SPV_OPT_DEF_BEFORE_USE) ? 1 : 0;
   hipStream_t s = static_cast<hipStream_t>(stream);
 
   int64_t plan_units = n_modules > p.n_tiles ? n_modules : p.n_tiles;
@@ -244,6 +251,10 @@ int run_validate(spv_ctx* ctx, const uint32_t* words, const int64_t* mod_off, in
     }
   }
   spv::launch_finalize(p, 2, s);
+  if (semantic && diag_flags) {
+    if ((r = check_launch(ctx))) return r;
+    spv::launch_diag(p, s);
+  }
   return check_launch(ctx);
 }
 
@@ -356,7 +367,8 @@ int spv_validate(spv_ctx* ctx, const uint32_t* words, const int64_t* mod_off, in
   if (!flags_ok(option_flags)) return SPV_ERR_INVALID_ARG;
   return run_validate(ctx, words, mod_off, n_modules, n_words, idx_off, idx_op, idx_cap, results,
                       (option_flags & SPV_OPT_NO_SEMANTIC) ? 0 : 1, ws, ws_bytes, stream, true,
-                      (option_flags & SPV_OPT_MODULE_RULES) != 0, (option_flags & SPV_OPT_DEBUG_CHECKS) != 0);
+                      (option_flags & SPV_OPT_MODULE_RULES) != 0, (option_flags & SPV_OPT_DEBUG_CHECKS) != 0,
+                      option_flags & (SPV_OPT_SEM_OFFSETS | SPV_OPT_DEF_BEFORE_USE));
 }
 
 int spv_validate_noalloc(spv_ctx* ctx, const uint32_t* words, const int64_t* mod_off, int64_t n_modules,
@@ -370,7 +382,8 @@ int spv_validate_noalloc(spv_ctx* ctx, const uint32_t* words, const int64_t* mod
   return run_validate(ctx, words, mod_off, n_modules, n_words, idx_off, idx_op, idx_cap, results,
                       (option_flags & SPV_OPT_NO_SEMANTIC) ? 0 : 1, ctx->scratch, size_t(SPV_NOALLOC_SCRATCH_BYTES),
                       stream, false, (option_flags & SPV_OPT_MODULE_RULES) != 0,
-                      (option_flags & SPV_OPT_DEBUG_CHECKS) != 0);
+                      (option_flags & SPV_OPT_DEBUG_CHECKS) != 0,
+                      option_flags & (SPV_OPT_SEM_OFFSETS | SPV_OPT_DEF_BEFORE_USE));
 }
 
 int spv_encode_bound(int64_t n_modules, int64_t n_records, int64_t n_opnd_words, int64_t n_string_records,

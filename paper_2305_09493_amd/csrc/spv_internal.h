@@ -79,7 +79,7 @@ static_assert(sizeof(ModState) == 48, "ModState layout");
 
 // ---- workspace layout ----------------------------------------------------
 struct Layout {
-  size_t ctrl, tileA, tileB, tfm, mods, idmap, tsum, lst, tres, rstate, p2list, total;
+  size_t ctrl, tileA, tileB, tfm, mods, idmap, tsum, lst, tres, rstate, p2list, diag, total;
 };
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -118,6 +118,8 @@ inline Layout make_layout(int64_t n_modules, int64_t n_words) {
   off = align256(off + 8 * kStateStride * size_t(n_tiles / kResolveTiles + 2));
   L.p2list = off;
   off = align256(off + 4 * size_t(n_tiles + n_modules + 2));
+  L.diag = off;
+  off = align256(off + 16 * size_t(n_modules + 1));
   L.total = off;
   return L;
 }
@@ -178,6 +180,12 @@ struct VParams {
   int sched_static;
   int p1_inline;  // k_pass2 computes finalize phase 1 itself (at most 256 modules; no k_finalize(1) launch)
   int rules;      // finalize applies the module-level rules
+  // semantic positions / defined-before-use (kernels of spv_diag.hip, after
+  // the finalize): per module, the first out-of-bound, duplicate and
+  // undefined offsets
+  uint4* diag;
+  int sem_offsets;
+  int before_use;
 };
 
 // Grammar entry for opcode < 256 (index 256 = any other opcode):
@@ -200,6 +208,7 @@ void launch_walk(const VParams& p, int grid, hipStream_t s);
 void launch_resolve(const VParams& p, hipStream_t s);
 void launch_finalize(const VParams& p, int phase, hipStream_t s);
 void launch_pass2(const VParams& p, int grid, hipStream_t s);
+void launch_diag(const VParams& p, hipStream_t s);
 
 struct EParams {
   const uint16_t* op;

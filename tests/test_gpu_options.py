@@ -74,6 +74,7 @@ def test_refused_option_bits():
     import paper_2305_09493_amd as spv
     b = _batch()
     w, mo = to_dev(b.words, b.mod_off)
-    for flags in (8, 16, 1 << 31, spv.OPT_NO_SEMANTIC | spv.OPT_MODULE_RULES):
+    for flags in (32, 64, 1 << 31, spv.OPT_NO_SEMANTIC | spv.OPT_MODULE_RULES,
+                  spv.OPT_NO_SEMANTIC | spv.OPT_SEM_OFFSETS, spv.OPT_NO_SEMANTIC | spv.OPT_DEF_BEFORE_USE):
         with pytest.raises(spv.SpvError):
             spv._run(True, w, mo, True, None, None, flags=flags)
