@@ -159,13 +159,22 @@ int spv_destroy(spv_ctx *ctx);
 const char *spv_last_hip_error(spv_ctx *ctx);
 
 /* Launch tuning (0 = keep the built-in default).  blocks_per_cu sets the
- * persistent grid of the single-pass decode/validate walk (a value above the
- * kernel's resident blocks per CU also turns off its cooperative, static tile
- * order); encode_block sets the records per encode block (a multiple of 256,
- * at most 4096, default 4096; SPV_ERR_INVALID_ARG otherwise). */
+ * persistent grid of the single-pass decode/validate walk (the fallback when
+ * some tile's entry cannot be settled in advance); encode_block sets the
+ * records per encode block (a multiple of 256, at most 4096, default 4096;
+ * SPV_ERR_INVALID_ARG otherwise). */
 int spv_set_tuning(spv_ctx *ctx, int blocks_per_cu, int encode_block);
 /* Current launch tuning of the context. */
 int spv_get_tuning(spv_ctx *ctx, int *blocks_per_cu, int *encode_block);
+
+/* Grids of the two kernels that run on every decode/validate call whose
+ * tiles settle (0 = keep): blocks per CU of the chain pass and of the
+ * resolved walk, each 1..64 (SPV_ERR_INVALID_ARG otherwise).  Both take
+ * their tiles in a static order, so any grid is correct; the default is the
+ * kernels' resident blocks per CU. */
+int spv_set_grids(spv_ctx *ctx, int chain_blocks_per_cu, int walk_blocks_per_cu);
+/* Current grids (blocks per CU) of the chain pass and the resolved walk. */
+int spv_get_grids(spv_ctx *ctx, int *chain_blocks_per_cu, int *walk_blocks_per_cu);
 
 /* Bytes of workspace that spv_decode / spv_validate need for a batch of
  * n_modules modules and n_words words (about 8 bytes per word plus small

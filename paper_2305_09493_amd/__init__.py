@@ -68,11 +68,14 @@ def load_library():
         lib.spv_decode_text.argtypes = [P, P, P, I64, I64, P, P, U32, P, I64, P, P, SZ, P]
         lib.spv_set_timing.argtypes = [P, ctypes.c_int]
         lib.spv_get_tuning.argtypes = [P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+        lib.spv_set_grids.argtypes = [P, ctypes.c_int, ctypes.c_int]
+        lib.spv_get_grids.argtypes = [P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
         lib.spv_read_timing.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)]
         for name in ("spv_create", "spv_destroy", "spv_set_tuning", "spv_workspace_size", "spv_decode",
                      "spv_validate", "spv_validate_noalloc", "spv_encode_bound", "spv_encode_workspace_size", "spv_encode",
                      "spv_records_workspace_size", "spv_decode_records", "spv_text_workspace_size", "spv_decode_text",
-                     "spv_set_timing", "spv_read_timing", "spv_get_tuning", "spv_server_create", "spv_server_start", "spv_server_submit",
+                     "spv_set_timing", "spv_read_timing", "spv_get_tuning", "spv_set_grids", "spv_get_grids",
+                     "spv_server_create", "spv_server_start", "spv_server_submit",
            "spv_server_poll", "spv_server_stats", "spv_server_destroy", "spv_server_cancel"):
             getattr(lib, name).restype = ctypes.c_int
         _lib = lib
@@ -82,7 +85,8 @@ def load_library():
 EXPORTS = ("spv_create", "spv_destroy", "spv_last_hip_error", "spv_set_tuning", "spv_workspace_size",
            "spv_decode", "spv_validate", "spv_validate_noalloc", "spv_encode_bound", "spv_encode_workspace_size", "spv_encode",
            "spv_records_workspace_size", "spv_decode_records", "spv_text_workspace_size", "spv_decode_text",
-           "spv_set_timing", "spv_read_timing", "spv_get_tuning", "spv_server_create", "spv_server_start", "spv_server_submit",
+           "spv_set_timing", "spv_read_timing", "spv_get_tuning", "spv_set_grids", "spv_get_grids",
+           "spv_server_create", "spv_server_start", "spv_server_submit",
            "spv_server_poll", "spv_server_stats", "spv_server_destroy", "spv_server_cancel")
 
 
@@ -126,6 +130,14 @@ class Context:
 
     def set_tuning(self, blocks_per_cu: int = 0, encode_block: int = 0):
         self.check(self.lib.spv_set_tuning(self.h, blocks_per_cu, encode_block), "spv_set_tuning")
+
+    def set_grids(self, chain_blocks_per_cu: int = 0, walk_blocks_per_cu: int = 0):
+        self.check(self.lib.spv_set_grids(self.h, chain_blocks_per_cu, walk_blocks_per_cu), "spv_set_grids")
+
+    def get_grids(self):
+        c, w = ctypes.c_int(), ctypes.c_int()
+        self.check(self.lib.spv_get_grids(self.h, ctypes.byref(c), ctypes.byref(w)), "spv_get_grids")
+        return c.value, w.value
 
     def get_tuning(self):
         """(blocks_per_cu, encode_block) currently in use."""

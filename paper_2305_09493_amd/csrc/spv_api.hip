@@ -341,6 +341,22 @@ int spv_set_tuning(spv_ctx* ctx, int blocks_per_cu, int encode_block) {
   return SPV_SUCCESS;
 }
 
+int spv_set_grids(spv_ctx* ctx, int chain_blocks_per_cu, int walk_blocks_per_cu) {
+  if (!ctx || chain_blocks_per_cu < 0 || chain_blocks_per_cu > 64 || walk_blocks_per_cu < 0 ||
+      walk_blocks_per_cu > 64)
+    return SPV_ERR_INVALID_ARG;
+  if (chain_blocks_per_cu > 0) ctx->chain_occ = chain_blocks_per_cu;
+  if (walk_blocks_per_cu > 0) ctx->walk_occ = walk_blocks_per_cu;
+  return SPV_SUCCESS;
+}
+
+int spv_get_grids(spv_ctx* ctx, int* chain_blocks_per_cu, int* walk_blocks_per_cu) {
+  if (!ctx || !chain_blocks_per_cu || !walk_blocks_per_cu) return SPV_ERR_INVALID_ARG;
+  *chain_blocks_per_cu = ctx->chain_occ;
+  *walk_blocks_per_cu = ctx->walk_occ;
+  return SPV_SUCCESS;
+}
+
 int spv_get_tuning(spv_ctx* ctx, int* blocks_per_cu, int* encode_block) {
   if (!ctx || !blocks_per_cu || !encode_block) return SPV_ERR_INVALID_ARG;
   *blocks_per_cu = ctx->blocks_per_cu;

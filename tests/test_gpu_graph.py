@@ -123,8 +123,50 @@ def test_encode_graph_capture_replays_match_eager():
         _ = torch.ones(1 << 20, device="cuda").sum().item()  # unrelated eager work between replays
 
 
+@pytest.mark.parametrize("grids", [(1, 1), (3, 12), (6, 6), (12, 3), (64, 64)])
+def test_parity_independent_of_chain_and_walk_grids(grids):
+    """The chain pass and the resolved walk take tiles in a static order: any
+    grid gives the same results and index."""
+    import paper_2305_09493_amd as spv
+    ctx = spv.context()
+    old = ctx.get_grids()
+    try:
+        ctx.set_grids(*grids)
+        assert ctx.get_grids() == grids
+        b = spvgen.config3(n_modules=96, n_faults=9, median=1200.0, hi=40_000)
+        compare(b.words, b.mod_off, label=f"chain, walk grids {grids}")
+        m = spvgen.gen_module(78, 300_000)
+        compare(m.words, [0, m.words.size], label=f"one module, chain, walk grids {grids}")
+    finally:
+        ctx.set_grids(*old)
+
+
+def test_grid_autotuner_picks_a_candidate_and_keeps_parity(tmp_path, monkeypatch):
+    import torch
+
+    import paper_2305_09493_amd as spv
+    from paper_2305_09493_amd import tune
+    monkeypatch.setenv("SPVGPU_TUNE_CACHE", str(tmp_path / "tune.json"))
+    ctx = spv.context()
+    old = ctx.get_grids()
+    try:
+        m = spvgen.gen_module(79, 200_000)
+        w = torch.from_numpy(m.words.view(np.int32)).cuda()
+        mo = torch.tensor([0, m.words.size], dtype=torch.int64, device="cuda")
+        r = tune.autotune_grids(w, mo, chain=(2, 6), walk=(3, 6))
+        assert (r["chain_blocks_per_cu"], r["walk_blocks_per_cu"]) in [(2, 3), (2, 6), (6, 3), (6, 6)]
+        ctx.set_grids(*old)
+        assert tune.apply("validate_grids", m.words.size)["walk_blocks_per_cu"] == r["walk_blocks_per_cu"]
+        assert ctx.get_grids() == (r["chain_blocks_per_cu"], r["walk_blocks_per_cu"])
+        compare(m.words, [0, m.words.size], label="after the grid autotuner")
+    finally:
+        ctx.set_grids(*old)
+
+
 @pytest.mark.parametrize("bpc", [1, 2, 8])
-def test_parity_independent_of_grid(bpc):
+def test_parity_independent_of_fallback_grid(bpc):
+    """blocks_per_cu sizes the single-pass fallback walk, which returns at
+    once on these inputs (every tile settles); crowded tiles below force it."""
     import paper_2305_09493_amd as spv
     ctx = spv.context()
     old = ctx.get_tuning()[0]
@@ -134,6 +176,10 @@ def test_parity_independent_of_grid(bpc):
         compare(b.words, b.mod_off, label=f"blocks_per_cu={bpc}")
         m = spvgen.gen_module(77, 120_000)
         compare(m.words, [0, m.words.size], label=f"one module, blocks_per_cu={bpc}")
+        # 6000 tiny modules: more than 63 modules overlap a tile, so the
+        # batch takes the single-pass walk with this grid
+        tiny = spvgen.pack([spvgen.gen_module([80, i], 5) for i in range(6000)])
+        compare(tiny.words, tiny.mod_off, label=f"crowded tiles, blocks_per_cu={bpc}")
     finally:
         ctx.set_tuning(blocks_per_cu=old)
 
