@@ -573,7 +573,7 @@ def main():
         for _ in range(3):
             g3.replay()
         torch.cuda.synchronize()
-        n_rep = 50
+        n_rep = 100
         rs = torch.cuda.current_stream()
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_rep)]
         tb0 = time.perf_counter()

@@ -332,17 +332,31 @@ __device__ __forceinline__ void put_string(S& s, const uint32_t* w, uint32_t nw)
   }
 }
 
+// An instruction's first word and the four words after it (loaded together,
+// before the line is built; words past the batch read as 0, words of the
+// next instruction are not used).
+struct InstWords {
+  uint32_t w[5];
+};
+
+__device__ __forceinline__ InstWords load_inst(const TParams& P, int64_t pos) {
+  InstWords iw;
+#pragma unroll
+  for (int q = 0; q < 5; ++q) iw.w[q] = pos + q < P.cap_inst ? P.words[pos + q] : 0u;
+  return iw;
+}
+
 // The text line of the instruction at word position pos of module m.
 template <class S>
 __device__ __forceinline__ void txt_line(const TParams& P, unsigned long long nslots, uint32_t m, int64_t pos,
-                                         S& s) {
-  const uint32_t w0 = P.words[pos], op = w0 & 0xFFFFu;
+                                         const InstWords& iw, S& s) {
+  const uint32_t w0 = iw.w[0], op = w0 & 0xFFFFu;
   const TxtOp d = txt_op(op);
   const uint32_t opt = P.options;
   const bool hl = (opt & kTxtHighlight) != 0, names = (opt & kTxtInlineNames) != 0;
   uint32_t v[4];
 #pragma unroll
-  for (uint32_t k = 0; k < 4; ++k) v[k] = k < d.nfix ? P.words[pos + 1 + k] : 0u;
+  for (uint32_t k = 0; k < 4; ++k) v[k] = k < d.nfix ? iw.w[1 + k] : 0u;
   bool has_res = false;
   uint32_t rv = 0;
 #pragma unroll
@@ -597,15 +611,31 @@ __global__ __launch_bounds__(kRecThreads) void k_txt_lens(TParams P) {
   for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
     txt_bracket(P, b, N, s_mb);
     unsigned long long sum = 0;
+    // the thread's four lines: positions, then all their words, then the
+    // lengths (the loads of the four are in flight together)
+    int64_t mk[kScanPerThread], pk[kScanPerThread];
+#pragma unroll
     for (int k = 0; k < kScanPerThread; ++k) {
       const int64_t r = b * kScanBlock + int64_t(k) * kRecThreads + tid;
+      mk[k] = 0;
+      pk[k] = -1;
       if (r < N) {
-        const int64_t m = txt_module(P.mscan, s_mb[0], s_mb[1], r);
-        const int64_t pos = txt_pos(P, m, r);
+        mk[k] = txt_module(P.mscan, s_mb[0], s_mb[1], r);
+        pk[k] = txt_pos(P, mk[k], r);
+      }
+    }
+    InstWords iw[kScanPerThread];
+#pragma unroll
+    for (int k = 0; k < kScanPerThread; ++k)
+      if (pk[k] >= 0) iw[k] = load_inst(P, pk[k]);
+#pragma unroll
+    for (int k = 0; k < kScanPerThread; ++k) {
+      const int64_t r = b * kScanBlock + int64_t(k) * kRecThreads + tid;
+      if (pk[k] >= 0) {
         CountSink c{0, nullptr};
-        txt_line(P, ns, uint32_t(m), pos, c);
+        txt_line(P, ns, uint32_t(mk[k]), pk[k], iw[k], c);
         P.lens[r] = c.o;
-        P.lpos[r] = uint32_t(pos);
+        P.lpos[r] = uint32_t(pk[k]);
         sum += c.o;
       }
     }
@@ -633,7 +663,7 @@ __global__ __launch_bounds__(kRecThreads) void k_txt_bscan(TParams P) {
 }
 
 // The lines.  lens[r] becomes line r's offset within its block of 1024.
-__global__ __launch_bounds__(kRecThreads) void k_txt_scatter(TParams P) {
+__global__ __launch_bounds__(kRecThreads, 5) void k_txt_scatter(TParams P) {
   __shared__ uint32_t s_stage[kStageBytes / 4];
   __shared__ int64_t s_mb[2];
   __shared__ unsigned long long s_w[kRecThreads / 64];
@@ -651,12 +681,24 @@ __global__ __launch_bounds__(kRecThreads) void k_txt_scatter(TParams P) {
     txt_bracket(P, b, N, s_mb);
     const unsigned long long bbase = P.btot[b];
     unsigned long long inblk = 0;  // bytes of the block's earlier slices
+    // the thread's four lines' lengths and positions first (loads in flight
+    // together); each slice's instruction words are loaded before its scan
+    uint32_t Lk[kScanPerThread], pk[kScanPerThread];
+#pragma unroll
+    for (int k = 0; k < kScanPerThread; ++k) {
+      const int64_t r = b * kScanBlock + int64_t(k) * kRecThreads + tid;
+      Lk[k] = r < N ? P.lens[r] : 0u;
+      pk[k] = r < N ? P.lpos[r] : 0u;
+    }
+#pragma unroll
     for (int k = 0; k < kScanPerThread; ++k) {
       const int64_t r0 = b * kScanBlock + int64_t(k) * kRecThreads;
       if (r0 >= N) break;  // (uniform over the block)
       const int64_t r = r0 + tid;
       const bool valid = r < N;
-      const uint32_t L = valid ? P.lens[r] : 0u;
+      const uint32_t L = Lk[k];
+      InstWords iwk;
+      if (valid) iwk = load_inst(P, int64_t(pk[k]));
       int64_t m = 0;
       if (valid) m = txt_module(P.mscan, s_mb[0], s_mb[1], r);
       unsigned long long inc = L;
@@ -687,10 +729,10 @@ __global__ __launch_bounds__(kRecThreads) void k_txt_scatter(TParams P) {
       if (valid) {
         if (staged) {
           LdsSink sk{stage, uint32_t(g - G0a), s_tok};
-          txt_line(P, ns, uint32_t(m), int64_t(P.lpos[r]), sk);
+          txt_line(P, ns, uint32_t(m), int64_t(pk[k]), iwk, sk);
         } else {
           GlobalSink sk{P.text, g, P.text_cap, 0u, s_tok};
-          txt_line(P, ns, uint32_t(m), int64_t(P.lpos[r]), sk);
+          txt_line(P, ns, uint32_t(m), int64_t(pk[k]), iwk, sk);
         }
       }
       __syncthreads();
