@@ -397,7 +397,8 @@ def main():
                     help="skip the leg of the validate call with the module-level rules")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg (Poisson stream, batched vs "
                                                             "one module per launch)")
-    ap.add_argument("--only-main", action="store_true", help="only the timed validate call (no other leg)")
+    ap.add_argument("--only-main", action="store_true",
+                    help="only the timed validate call with the default grids (no other leg, no autotuning)")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default grids instead of autotuning the chain-pass and walk grids first")
     ap.add_argument("--serve-rates", default="20000", help="comma-separated arrival rates for --serve")
@@ -408,7 +409,7 @@ def main():
     args = ap.parse_args()
     if args.only_main:
         args.no_cpu = args.no_batched = args.no_encode = args.no_records = args.no_text = True
-        args.no_module_rules = args.no_serve = True
+        args.no_module_rules = args.no_serve = args.no_tune = True
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path (batches would shard by a "
