@@ -497,6 +497,7 @@ int spv_decode_text(spv_ctx* ctx, const uint32_t* words, const int64_t* mod_off,
   p.slot_cap = L.slot_cap;
   p.nlist = reinterpret_cast<uint2*>(base + L.nlist);
   p.bcount = reinterpret_cast<uint32_t*>(base + L.bcount);
+  p.nfilter = reinterpret_cast<uint32_t*>(base + L.nfilter);
   spv::launch_text(p, static_cast<hipStream_t>(stream));
   return check_launch(ctx);
 }

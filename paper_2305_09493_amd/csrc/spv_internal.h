@@ -356,9 +356,11 @@ struct TParams {
   int64_t slot_cap;
   uint2* nlist;                 // OpName instructions (module, word position), 1024 entries per block
   uint32_t* bcount;             // OpName instructions per block of 1024 instructions
+  uint32_t* nfilter;            // kTxtFilterBits bits: a (module, ID) that some OpName targets has its bit set
 };
+constexpr uint32_t kTxtFilterBits = 1u << 24;  // 2 MB: stays in L2
 struct TLayout {
-  size_t ctrl, mscan, mstate, lens, lpos, btot, bstate, slots, nlist, bcount, total;
+  size_t ctrl, mscan, mstate, lens, lpos, btot, bstate, slots, nlist, bcount, nfilter, total;
   int64_t slot_cap;
 };
 inline TLayout make_tlayout(int64_t n_modules, int64_t n_words, uint32_t options) {
@@ -391,6 +393,8 @@ inline TLayout make_tlayout(int64_t n_modules, int64_t n_words, uint32_t options
   off = align256(off + (names ? 8 * size_t(nb) * 1024 : 0));
   L.bcount = off;
   off = align256(off + (names ? 4 * size_t(nb) : 0));
+  L.nfilter = off;
+  off = align256(off + (names ? size_t(kTxtFilterBits) / 8 : 0));
   L.total = off;
   return L;
 }

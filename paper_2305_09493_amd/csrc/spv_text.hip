@@ -29,7 +29,8 @@
 // header bytes; with inline names, the OpName instructions are gathered into
 // per-block regions of a list and inserted into an open-addressing hash keyed
 // by (module, ID), where a 64-bit atomicMin on (position, name length) keeps
-// each ID's first OpName; a length pass sizes every
+// each ID's first OpName, and into a 2 MB bit filter that answers most IDs
+// (those without a name) without a probe of the table; a length pass sizes every
 // line (the same line writer run into a counting sink) and totals blocks of
 // 1024 lines; a scan of those totals and an in-block scan in the scatter place
 // every line.  The scatter writes a slice of 256 lines into LDS at the byte
@@ -235,9 +236,17 @@ __device__ __forceinline__ unsigned long long txt_slots(const TParams& P) {
   return s < (unsigned long long)P.slot_cap ? s : (unsigned long long)P.slot_cap;
 }
 
+// Bit of (module, ID) in the name filter: the mixed key's high bits (the
+// table slot takes its low bits).
+__device__ __forceinline__ uint32_t txt_fbit(unsigned long long mixed) { return uint32_t(mixed >> 40); }
+
 __device__ __forceinline__ IdName txt_name(const TParams& P, unsigned long long nslots, uint32_t m, uint32_t v) {
   const unsigned long long key = ((unsigned long long)m << 32) | v;
-  unsigned long long h = txt_mix(key) & (nslots - 1);
+  const unsigned long long mixed = txt_mix(key);
+  // most IDs have no name: the filter (in L2) answers them without a probe
+  const uint32_t fb = txt_fbit(mixed);
+  if (!((P.nfilter[fb >> 5] >> (fb & 31u)) & 1u)) return IdName{0u, 0u};
+  unsigned long long h = mixed & (nslots - 1);
   while (true) {  // the table is at most half full, so an empty slot ends every probe
     const unsigned long long k = P.slots[h].key;
     if (k == key) {
@@ -555,6 +564,7 @@ __global__ __launch_bounds__(kRecThreads) void k_txt_hclear(TParams P) {
     P.slots[i].key = kTxtEmpty;
     P.slots[i].pl = ~0ull;
   }
+  for (unsigned long long i = gtid; i < kTxtFilterBits / 32; i += nth) P.nfilter[i] = 0u;
 }
 
 // Inline names, step 4: insert every OpName by (module, target) with its
@@ -587,7 +597,10 @@ __global__ __launch_bounds__(kRecThreads) void k_txt_insert(TParams P) {
     }
     const unsigned long long val = ((unsigned long long)e.y << 32) | (ok ? len : 0u);
     const unsigned long long key = ((unsigned long long)e.x << 32) | P.words[e.y + 1];
-    unsigned long long h = txt_mix(key) & (ns - 1);
+    const unsigned long long mixed = txt_mix(key);
+    const uint32_t fb = txt_fbit(mixed);
+    atomicOr(&P.nfilter[fb >> 5], 1u << (fb & 31u));
+    unsigned long long h = mixed & (ns - 1);
     while (true) {
       const unsigned long long prev = atomicCAS(&P.slots[h].key, kTxtEmpty, key);
       if (prev == kTxtEmpty || prev == key) {
@@ -791,7 +804,8 @@ void launch_text(const TParams& p, hipStream_t s) {
   if (p.options & kTxtInlineNames) {
     hipLaunchKernelGGL(k_txt_collect, dim3(gb), dim3(kRecThreads), 0, s, p);
     hipLaunchKernelGGL(k_txt_ncount, dim3(1), dim3(1024), 0, s, p);
-    hipLaunchKernelGGL(k_txt_hclear, dim3(grid(p.slot_cap)), dim3(kRecThreads), 0, s, p);
+    hipLaunchKernelGGL(k_txt_hclear, dim3(grid(p.slot_cap > int64_t(kTxtFilterBits / 32) ? p.slot_cap : int64_t(kTxtFilterBits / 32))),
+                       dim3(kRecThreads), 0, s, p);
     hipLaunchKernelGGL(k_txt_insert, dim3(grid(p.cap_inst)), dim3(kRecThreads), 0, s, p);
   }
   hipLaunchKernelGGL(k_txt_lens, dim3(gb), dim3(kRecThreads), 0, s, p);
