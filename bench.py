@@ -455,7 +455,8 @@ def main():
 
     # autotuner: the grids of the chain pass and the resolved walk, timed on
     # this module before the warm-up (the timed region uses the choice)
-    tuning = {"chain_blocks_per_cu": ctx.get_grids()[0], "walk_blocks_per_cu": ctx.get_grids()[1],
+    lib_grids = ctx.get_grids()  # the library's default: each kernel's resident blocks per CU
+    tuning = {"chain_blocks_per_cu": lib_grids[0], "walk_blocks_per_cu": lib_grids[1],
               "source": "default (resident blocks per CU)"}
     if not args.no_tune:
         from paper_2305_09493_amd import tune
@@ -558,10 +559,11 @@ def main():
                    "walk_blocks_per_cu": tuning["walk_blocks_per_cu"], "source": tuning["source"]}
         if not args.no_tune:
             from paper_2305_09493_amd import tune
+            ctx.set_grids(*lib_grids)  # (the sweep reports the library default as its baseline)
             tr = tune.autotune_grids(w3, m3, save=False)
             tuning3 = {"chain_blocks_per_cu": tr["chain_blocks_per_cu"],
                        "walk_blocks_per_cu": tr["walk_blocks_per_cu"], "source": "autotuned on this batch",
-                       "ms": tr["ms"], "default_ms": tr["default_ms"]}
+                       "ms": tr["ms"], "default": tr["default"], "default_ms": tr["default_ms"]}
         for _ in range(3):
             spv.validate(w3, m3, ctx=ctx, out=(r3, i3, p3), workspace=ws3)
         torch.cuda.synchronize()
