@@ -174,9 +174,9 @@ struct VParams {
   uint32_t* p2list;  // tiles of the modules that need the undefined-ID pass
   int semantic;
   int index;
-  // 1: tile t is processed by block t mod gridDim.x (the grid is launched
-  // cooperatively, so every block is resident); 0: tiles are claimed in
-  // order from a counter
+  // single-pass walk: 1, tile t is processed by block t mod gridDim.x; 0,
+  // tiles are claimed in order from a counter (the resolved walk always takes
+  // tiles t, t + gridDim.x, ...: its tiles do not wait on each other)
   int sched_static;
   int p1_inline;  // k_pass2 computes finalize phase 1 itself (at most 256 modules; no k_finalize(1) launch)
   int rules;      // finalize applies the module-level rules

@@ -222,7 +222,7 @@ struct Shared {
 
 // Shared state of the resolved walk: no staging of index entries (they are
 // written directly), OpName starts in a short list (a tile with more checks
-// its strings lane by lane), so that five blocks fit on a CU.
+// its strings lane by lane), so that six blocks fit on a CU.
 constexpr int kNameCap = 1024;
 struct WalkShared {
   uint32_t tw[kTwSize] __attribute__((aligned(16)));
@@ -1318,10 +1318,6 @@ __device__ __forceinline__ void main_body(SH& S, const VParams& P) {
   uint4 pf[kLaneWords / 4];
   uint32_t pf_tail = 0;  // (threads below kTwTail) a word past the next tile's end
   long long pf_tile = -1;
-  // resolved walk: the next tile's lane record, entry, prefix and first-lane
-  // chain, loaded with its words
-  uint32_t pr_rec = 0, pr_E = kExitDead, pr_pre = 0, pr_m0 = 0;
-  long long pr_tile = -1;
 
   for (;;) {
     __syncthreads();
@@ -1440,14 +1436,13 @@ __device__ __forceinline__ void main_body(SH& S, const VParams& P) {
     if constexpr (kRes) {
       // starts and parse-error nodes from the chain pass; the first lane adds
       // the part of its candidate chain that its resolved entry reaches
-      const bool pr = pr_tile == t;
-      const uint32_t rec = pr ? pr_rec : P.lst[t * kBlock + tid];
-      res_pre = pr ? pr_pre : P.tres[2 * t + 1];
+      const uint32_t rec = P.lst[t * kBlock + tid];
+      res_pre = P.tres[2 * t + 1];
       starts = rec & 0xFFFFu;
       errs = rec >> 16;
       if (tid == 0) {
-        const uint32_t Et = pr ? pr_E : P.tres[2 * t];
-        const uint32_t m0 = pr ? pr_m0 : P.tsum[4 * t + 1];
+        const uint32_t Et = P.tres[2 * t];
+        const uint32_t m0 = P.tsum[4 * t + 1];
         const uint32_t h0 = L.hdr ? uint32_t(__builtin_ctz(L.hdr)) : 16u;
         if (Et < 14u && Et < h0) {
           if ((m0 >> Et) & 1u) {
@@ -1619,9 +1614,9 @@ __device__ __forceinline__ void main_body(SH& S, const VParams& P) {
     }
     if (tid == kBlock - 1) S.tnext = claim_tn;
     __syncthreads();
-    // the next tile's words (and, in the resolved walk, its records): the
-    // single-pass walk loads them here; the resolved walk, which runs more
-    // blocks per CU, after its result-ID checks (fewer live registers there)
+    // the next tile's words, loaded during the rest of this one (the
+    // single-pass walk only: the resolved walk runs more blocks per CU and
+    // hides the load latency with them instead of with registers)
     auto issue_prefetch = [&]() {
       const long long tn = S.tnext;
       const int64_t an = tn * kTileWords + int64_t(tid) * kLaneWords;
@@ -1645,13 +1640,6 @@ __device__ __forceinline__ void main_body(SH& S, const VParams& P) {
           pf_tail = (e1 + tid < P.W) ? P.words[e1 + tid] : 0u;
         }
         pf_tile = tn;
-      }
-      if (kRes && tn < P.n_tiles) {
-        pr_rec = P.lst[tn * kBlock + tid];
-        pr_E = P.tres[2 * tn];
-        pr_pre = P.tres[2 * tn + 1];
-        pr_m0 = P.tsum[4 * tn + 1];
-        pr_tile = tn;
       }
     };
     if constexpr (!kRes) issue_prefetch();
