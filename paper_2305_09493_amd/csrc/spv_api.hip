@@ -180,8 +180,9 @@ int run_validate(spv_ctx* ctx, const uint32_t* words, const int64_t* mod_off, in
   p.semantic = semantic;
   p.index = index ? 1 : 0;
   p.sched_static = 0;
-  // small batches: the second pass decides its own work (no phase-1 launch)
-  p.p1_inline = (semantic && n_modules <= 256 && p.n_tiles > 0) ? 1 : 0;
+  // small batches (a module per thread of one block): the second pass decides
+  // its own work and writes the results (no finalize launch)
+  p.p1_inline = (semantic && n_modules <= spv::kBlock && p.n_tiles > 0) ? 1 : 0;
   p.rules = rules ? 1 : 0;
   p.diag = reinterpret_cast<uint4*>(base + L.diag);
   p.sem_offsets = (diag_flags & SPV_OPT_SEM_OFFSETS) ? 1 : 0;
@@ -250,7 +251,8 @@ int run_validate(spv_ctx* ctx, const uint32_t* words, const int64_t* mod_off, in
       if ((r = check_launch(ctx))) return r;
     }
   }
-  spv::launch_finalize(p, 2, s);
+  // (small batches: the second pass's last block wrote the results)
+  if (!p.p1_inline) spv::launch_finalize(p, 2, s);
   if (semantic && diag_flags) {
     if ((r = check_launch(ctx))) return r;
     spv::launch_diag(p, s);

@@ -134,6 +134,7 @@ enum {
   kCtlClaimR = 5,
   kCtlDoneR = 6,
   kCtlP2Tiles = 7,  // entries of the second pass's tile list
+  kCtlP2Done = 8,   // blocks of the second pass that have finished (small batches)
   kCtlDebug = 15    // status word of the SPV_OPT_DEBUG_CHECKS offset check
 };
 // kCtlMode: kModeResolved when the chain and resolve passes settled every
@@ -178,7 +179,9 @@ struct VParams {
   // tiles are claimed in order from a counter (the resolved walk always takes
   // tiles t, t + gridDim.x, ...: its tiles do not wait on each other)
   int sched_static;
-  int p1_inline;  // k_pass2 computes finalize phase 1 itself (at most 256 modules; no k_finalize(1) launch)
+  // at most 256 modules: k_pass2 computes finalize phase 1 itself and its
+  // last block writes the results (no k_finalize launch at all)
+  int p1_inline;
   int rules;      // finalize applies the module-level rules
   // semantic positions / defined-before-use (kernels of spv_diag.hip, after
   // the finalize): per module, the first out-of-bound, duplicate and

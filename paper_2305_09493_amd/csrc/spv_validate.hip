@@ -905,6 +905,7 @@ __global__ __launch_bounds__(256) void k_plan(VParams P, int64_t chunk) {
     P.ctrl[kCtlClaimR] = 0;
     P.ctrl[kCtlDoneR] = 0;
     P.ctrl[kCtlP2Tiles] = 0;
+    P.ctrl[kCtlP2Done] = 0;
   }
   for (int64_t m = gtid; m < P.M; m += nth) {
     int64_t off = P.mod_off[m], end = P.mod_off[m + 1];
@@ -2098,63 +2099,69 @@ __global__ __launch_bounds__(kBlock, 24 / kWaves) void k_walk(VParams P) {
 }
 
 // ---------------------------------------------------------------------------
+// Result of module m from its state (the second finalize phase).
+__device__ __forceinline__ void finalize_module(const VParams& P, int64_t m) {
+  const ModState& ms = P.mods[m];
+  spv_result r;
+  if (ms.hdr_code != 0) {
+    r.code = ms.hdr_code;
+    r.sem_mask = 0;
+    r.err_word = ms.hdr_err;
+    r.n_inst = 0;
+  } else if (ms.err_key != ~0ull) {
+    r.code = uint32_t(ms.err_key & 0xFFu);
+    r.sem_mask = 0;
+    r.err_word = uint32_t(ms.err_key >> 8);
+    r.n_inst = uint32_t(ms.err_rank & 0xFFFFFFFFu);
+  } else {
+    uint32_t sem = P.semantic ? (ms.flags & 7u) : 0u;
+    r.code = (sem & 1u) ? SPV_E_ID_OUT_OF_BOUND : (sem & 2u) ? SPV_E_DUPLICATE_ID : (sem & 4u) ? SPV_E_UNDEFINED_ID : 0u;
+    r.sem_mask = sem;
+    r.err_word = 0xFFFFFFFFu;
+    r.n_inst = ms.n_total;
+    if (P.rules && r.code == 0) {
+      // module-level rules (section "Validation Rules"): a capability, the
+      // memory model, a function and an entry point
+      const uint32_t present = (ms.flags >> kModRuleShift) & 15u;
+      const uint32_t missing = ((present & 1u) ? 0u : 8u) | ((present & 2u) ? 0u : 16u) |
+                               ((present & 4u) ? 0u : 32u) | ((present & 8u) ? 0u : 64u);
+      if (missing) {
+        r.code = SPV_E_MODULE_RULES;
+        r.sem_mask = missing;
+      }
+    }
+  }
+  if (P.ctrl[kCtlSpinErr]) r.code = kSpinFailCode;
+  P.results[m] = r;
+}
+
 // finalize: phase 1 marks modules whose undefined-ID check needs the second
 // pass; phase 2 writes spv_result.
 __global__ __launch_bounds__(256) void k_finalize(VParams P, int phase) {
   const int64_t gtid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const int64_t nth = int64_t(gridDim.x) * blockDim.x;
   for (int64_t m = gtid; m < P.M; m += nth) {
-    ModState& ms = P.mods[m];
-    if (phase == 1) {
-      if (ms.hdr_code == 0 && ms.err_key == ~0ull) {
-        bool need;
-        if (ms.flags & kModSparse) need = true;
-        else need = ms.bound > 1u && ms.def_count < ms.bound - 1u;
-        if (need) {
-          ms.flags |= kModPass2;
-          atomicAdd(&P.ctrl[kCtlPass2], 1u);
-          // the module's tiles join the second pass's list
-          const int64_t off = P.mod_off[m], end = P.mod_off[m + 1];
-          if (end > off) {
-            const int64_t a = off / kTileWords, b = (end - 1) / kTileWords;
-            const uint32_t base = atomicAdd(&P.ctrl[kCtlP2Tiles], uint32_t(b - a + 1));
-            for (int64_t i = 0; i <= b - a; ++i) P.p2list[base + i] = uint32_t(a + i);
-          }
-        }
-      }
+    if (phase == 2) {
+      finalize_module(P, m);
       continue;
     }
-    spv_result r;
-    if (ms.hdr_code != 0) {
-      r.code = ms.hdr_code;
-      r.sem_mask = 0;
-      r.err_word = ms.hdr_err;
-      r.n_inst = 0;
-    } else if (ms.err_key != ~0ull) {
-      r.code = uint32_t(ms.err_key & 0xFFu);
-      r.sem_mask = 0;
-      r.err_word = uint32_t(ms.err_key >> 8);
-      r.n_inst = uint32_t(ms.err_rank & 0xFFFFFFFFu);
-    } else {
-      uint32_t sem = P.semantic ? (ms.flags & 7u) : 0u;
-      r.code = (sem & 1u) ? SPV_E_ID_OUT_OF_BOUND : (sem & 2u) ? SPV_E_DUPLICATE_ID : (sem & 4u) ? SPV_E_UNDEFINED_ID : 0u;
-      r.sem_mask = sem;
-      r.err_word = 0xFFFFFFFFu;
-      r.n_inst = ms.n_total;
-      if (P.rules && r.code == 0) {
-        // module-level rules (section "Validation Rules"): a capability, the
-        // memory model, a function and an entry point
-        const uint32_t present = (ms.flags >> kModRuleShift) & 15u;
-        const uint32_t missing = ((present & 1u) ? 0u : 8u) | ((present & 2u) ? 0u : 16u) |
-                                 ((present & 4u) ? 0u : 32u) | ((present & 8u) ? 0u : 64u);
-        if (missing) {
-          r.code = SPV_E_MODULE_RULES;
-          r.sem_mask = missing;
+    ModState& ms = P.mods[m];
+    if (ms.hdr_code == 0 && ms.err_key == ~0ull) {
+      bool need;
+      if (ms.flags & kModSparse) need = true;
+      else need = ms.bound > 1u && ms.def_count < ms.bound - 1u;
+      if (need) {
+        ms.flags |= kModPass2;
+        atomicAdd(&P.ctrl[kCtlPass2], 1u);
+        // the module's tiles join the second pass's list
+        const int64_t off = P.mod_off[m], end = P.mod_off[m + 1];
+        if (end > off) {
+          const int64_t a = off / kTileWords, b = (end - 1) / kTileWords;
+          const uint32_t base = atomicAdd(&P.ctrl[kCtlP2Tiles], uint32_t(b - a + 1));
+          for (int64_t i = 0; i <= b - a; ++i) P.p2list[base + i] = uint32_t(a + i);
         }
       }
     }
-    if (P.ctrl[kCtlSpinErr]) r.code = kSpinFailCode;
-    P.results[m] = r;
   }
 }
 
@@ -2165,7 +2172,8 @@ __global__ __launch_bounds__(kBlock) void k_pass2(VParams P) {
   // small batches (p1_inline, at most kBlock modules): every block decides
   // for itself which modules the pass needs and lists their tiles in LDS
   // (the first finalize phase's work, no launch of it); the need flags are
-  // read from LDS, never from module state that other blocks write
+  // read from LDS, never from module state that other blocks write.  The
+  // second finalize phase runs at the end, in one block.
   __shared__ uint32_t s_need[kBlock / 32];
   __shared__ uint32_t s_tpre[kBlock + 1];  // listed tiles before module m
   const int tid = threadIdx.x;
@@ -2199,7 +2207,10 @@ __global__ __launch_bounds__(kBlock) void k_pass2(VParams P) {
     if (tid == 0) s_tpre[kBlock] = tot;
     __syncthreads();
     n_list = tot;
-    if (n_list == 0) return;  // the same in every block
+    if (n_list == 0) {  // the same in every block: no second pass, block 0 writes the results
+      if (blockIdx.x == 0 && tid < P.M) finalize_module(P, tid);
+      return;
+    }
   } else {
     if (P.ctrl[kCtlPass2] == 0) return;
     n_list = P.ctrl[kCtlP2Tiles];
@@ -2408,6 +2419,20 @@ __global__ __launch_bounds__(kBlock) void k_pass2(VParams P) {
       }
     }
     __syncthreads();
+  }
+  if (P.p1_inline) {
+    // the last block to finish writes the results: every block's module-state
+    // updates are complete and visible (fence, barrier) before it counts
+    // itself, and the last one reads them after its own fence
+    __shared__ uint32_t s_last;
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) s_last = (atomicAdd(&P.ctrl[kCtlP2Done], 1u) == gridDim.x - 1) ? 1u : 0u;
+    __syncthreads();
+    if (s_last) {
+      __threadfence();
+      if (tid < P.M) finalize_module(P, tid);
+    }
   }
 }
 
