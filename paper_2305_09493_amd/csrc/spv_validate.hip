@@ -116,6 +116,33 @@ __device__ __forceinline__ void st_state(unsigned long long* p, unsigned long lo
 
 __device__ __forceinline__ int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
 
+// Module of word x: the last m < M with mod_off[m] <= x (mod_off[0] = 0 <= x).
+// An 8-way search: each round loads seven probes together and keeps the
+// eighth of the range that holds the answer, so a batch of 4096 modules takes
+// five rounds of loads instead of a binary search's twelve.
+__device__ __forceinline__ int64_t find_module(const int64_t* mod_off, int64_t M, int64_t x) {
+  int64_t lo = 0, hi = M - 1;  // mod_off[lo] <= x, answer in [lo, hi]
+  while (hi - lo >= 8) {
+    const int64_t step = (hi - lo + 1) >> 3;
+    int64_t v[7];
+#pragma unroll
+    for (int k = 0; k < 7; ++k) v[k] = mod_off[lo + (k + 1) * step];
+    int n = 0;  // probes at or below x (a prefix: the offsets do not decrease)
+#pragma unroll
+    for (int k = 0; k < 7; ++k) n += v[k] <= x ? 1 : 0;
+    const int64_t nlo = lo + n * step;
+    if (n < 7) hi = nlo + step - 1;
+    lo = nlo;
+  }
+  int64_t v[7];
+#pragma unroll
+  for (int k = 0; k < 7; ++k) v[k] = (lo + 1 + k <= hi) ? mod_off[lo + 1 + k] : INT64_MAX;
+  int n = 0;
+#pragma unroll
+  for (int k = 0; k < 7; ++k) n += v[k] <= x ? 1 : 0;
+  return lo + n;
+}
+
 // A string operand: bytes little-endian within each word, terminated by the
 // first NUL, which must be in the last word, followed only by NUL padding.
 __device__ __forceinline__ bool string_ok_global(const uint32_t* w, int64_t n_words) {
@@ -943,14 +970,7 @@ __global__ __launch_bounds__(256) void k_plan(VParams P, int64_t chunk) {
     P.tileA[(t) * kStateStride] = 0;
     P.tileB[(t) * kStateStride] = 0;
     // module containing word t * T: last m with mod_off[m] <= tT
-    int64_t x = t * kTileWords;
-    int64_t lo = 0, hi = P.M - 1;
-    while (lo < hi) {
-      int64_t mid = (lo + hi + 1) >> 1;
-      if (P.mod_off[mid] <= x) lo = mid;
-      else hi = mid - 1;
-    }
-    P.tfm[t] = int32_t(lo);
+    P.tfm[t] = int32_t(find_module(P.mod_off, P.M, t * kTileWords));
   }
   if (!P.semantic) return;
   // clear the ID sets of header-valid modules, chunk by chunk of idmap
@@ -958,15 +978,7 @@ __global__ __launch_bounds__(256) void k_plan(VParams P, int64_t chunk) {
   int64_t n_chunks = (P.W + chunk - 1) / chunk;
   for (int64_t c = blockIdx.x; c < n_chunks; c += gridDim.x) {
     int64_t cs = c * chunk, ce = cs + chunk < P.W ? cs + chunk : P.W;
-    if (threadIdx.x == 0) {
-      int64_t lo = 0, hi = P.M - 1;
-      while (lo < hi) {
-        int64_t mid = (lo + hi + 1) >> 1;
-        if (P.mod_off[mid] <= cs) lo = mid;
-        else hi = mid - 1;
-      }
-      s_m0 = lo;
-    }
+    if (threadIdx.x == 0) s_m0 = find_module(P.mod_off, P.M, cs);
     __syncthreads();
     for (int64_t m = s_m0; m < P.M; ++m) {
       int64_t off = P.mod_off[m], end = P.mod_off[m + 1];
@@ -2220,6 +2232,8 @@ __global__ __launch_bounds__(kBlock) void k_pass2(VParams P) {
   };
   if (threadIdx.x == 0) S.cache_ok = 0;
   init_table(S.tbl);
+  // the resolved walk ran (the chain pass's lane records are exact)
+  const bool resolved = P.ctrl[kCtlMode] == kModeResolved;
   // tiles of the marked modules, listed by the first finalize phase, in
   // block order (a tile of two marked modules may come twice: the checks
   // only set flags)
@@ -2287,13 +2301,60 @@ __global__ __launch_bounds__(kBlock) void k_pass2(VParams P) {
     // bitmap-mode modules: walk the chain from the exact entry and test uses
     uint32_t E;
     if (S.list[0].rel == 0 || t == 0) E = kExitDead;
-    else if (P.ctrl[kCtlMode] == kModeResolved) E = P.tres[2 * t];
+    else if (resolved) E = P.tres[2 * t];
     else {
       unsigned long long st = ld_state(&P.tileA[(t - 1) * kStateStride]);
       E = uint32_t(st);
     }
     bool serial = S.crowded || (E != kExitDead && E >= kFar);
-    if (!serial) {
+    // uses of the lane's starts (use slots as bits 1..19 of the lane window;
+    // those past the lane go to the next one): each use of a marked
+    // bitmap-mode module must be a set bit of its bitmap (block-wide: every
+    // thread calls it)
+    auto test_uses = [&](const Lane& L, uint32_t usem) {
+      S.spill[tid] = (usem >> 16) & 0xFu;
+      __syncthreads();
+      if (tid > 0) usem |= S.spill[tid - 1];
+      auto test = [&](int jm, uint32_t v) {
+        const LEnt& le = S.list[jm];
+        if (le.mod < 0 || (le.info & kInfoSparse) || !(le.info & kInfoHdrOk)) return;
+        ModState& ms = P.mods[le.mod];
+        if (!marked(le.mod)) return;
+        if (v == 0u || v >= le.bound) return;
+        unsigned long long word = P.idmap[le.off + (v >> 6)];
+        if (!((word >> (v & 63u)) & 1ull)) atomicOr(&ms.flags, kModUndef);
+      };
+#pragma unroll
+      for (int p = 0; p < kLaneWords; ++p)
+        if ((usem >> p) & 1u) test(lane_mod_at(L, p), L.w[p]);
+      if (tid == kBlock - 1) {
+        uint32_t sp = S.spill[tid];
+        for (int k = 0; k < 4; ++k)
+          if ((sp >> k) & 1u) test(lane_mod_at(L, 15), P.words[L.a + 16 + k]);
+      }
+    };
+    if (!serial && resolved) {
+      // resolved batches: the chain pass's lane starts give the instruction
+      // starts (the first lane adds the part of its candidate chain that the
+      // resolved entry reaches, as the resolved walk does), so the lanes need
+      // no transfer functions
+      Lane L;
+      L.a = t0 + int64_t(tid) * kLaneWords;
+#pragma unroll
+      for (int i = 0; i < kLaneWords; ++i) L.w[i] = (L.a + i < P.W) ? P.words[L.a + i] : 0u;
+      lane_window(S, L, tid * kLaneWords);
+      uint32_t starts = P.lst[t * kBlock + tid] & 0xFFFFu;
+      if (tid == 0) {
+        const uint32_t m0 = P.tsum[4 * t + 1];
+        const uint32_t h0 = L.hdr ? uint32_t(__builtin_ctz(L.hdr)) : 16u;
+        if (E < 14u && E < h0 && ((m0 >> E) & 1u)) starts |= m0 & 0xFFFFu & (~0u << E);
+      }
+      uint32_t usem = 0;
+#pragma unroll
+      for (int p = 0; p < kLaneWords; ++p)
+        if ((starts >> p) & 1u) usem |= (tbl_lookup(S.tbl, L.w[p] & 0xFFFFu) >> 28) << (p + 1);
+      test_uses(L, usem);
+    } else if (!serial) {
       Lane L;
       L.a = t0 + int64_t(tid) * kLaneWords;
 #pragma unroll
@@ -2345,26 +2406,7 @@ __global__ __launch_bounds__(kBlock) void k_pass2(VParams P) {
 #pragma unroll
           for (int p = 0; p < kLaneWords; ++p)
             if ((starts >> p) & 1u) usem |= ((L.rolep[p >> 2] >> (8 * (p & 3) + 4)) & 0xFu) << (p + 1);
-          S.spill[tid] = (usem >> 16) & 0xFu;
-          __syncthreads();
-          if (tid > 0) usem |= S.spill[tid - 1];
-          auto test = [&](int jm, uint32_t v) {
-            const LEnt& le = S.list[jm];
-            if (le.mod < 0 || (le.info & kInfoSparse) || !(le.info & kInfoHdrOk)) return;
-            ModState& ms = P.mods[le.mod];
-            if (!marked(le.mod)) return;
-            if (v == 0u || v >= le.bound) return;
-            unsigned long long word = P.idmap[le.off + (v >> 6)];
-            if (!((word >> (v & 63u)) & 1ull)) atomicOr(&ms.flags, kModUndef);
-          };
-#pragma unroll
-          for (int p = 0; p < kLaneWords; ++p)
-            if ((usem >> p) & 1u) test(lane_mod_at(L, p), L.w[p]);
-          if (tid == kBlock - 1) {
-            uint32_t sp = S.spill[tid];
-            for (int k = 0; k < 4; ++k)
-              if ((sp >> k) & 1u) test(lane_mod_at(L, 15), P.words[L.a + 16 + k]);
-          }
+          test_uses(L, usem);
         }
       }
       serial = amb;
