@@ -3,7 +3,9 @@ OpName and OpEntryPoint of 4095 to 65535 words placed at chosen offsets
 within the kernels' 4096-word tiles (at a tile start, just after one, in the
 middle, and ending exactly on a tile boundary), two long ones back to back,
 and long names with a malformed terminator.  Decode, validate and records
-mode are each compared with the oracle element by element."""
+mode are each compared with the oracle element by element.  Such batches
+take the single-pass walk; the second pass (undefined-ID search) is checked
+there and in a batch without a long instruction."""
 import numpy as np
 import pytest
 
@@ -148,3 +150,51 @@ def test_long_name_with_bad_terminator(bad):
     o = oracle.validate(words, mod_off, semantic=True, index=False)
     assert int(np.sum(o["code"] == oracle.E_BAD_STRING)) == 3, o["code"]
     _check_all(words, mod_off, f"bad terminator {bad}")
+
+
+def _pass2_modules(seed):
+    """Generated modules whose result IDs do not cover [1, bound), so the
+    second pass tests their uses: a raised bound with every use defined, a
+    raised bound with a use of an undefined ID below it, and a duplicate
+    result ID (the ID it replaces is left undefined)."""
+    mods, want = [], []
+    for i in range(6):
+        m = spvgen.gen_module([seed, i], 2500)
+        w = m.words.copy()
+        upos, dpos = [], []
+        for k in range(spvgen.N_PROLOGUE, m.n_inst):
+            for s, r in enumerate(spvgen.ROLES[m.kind[k]]):
+                if r == "U":
+                    upos.append(int(m.starts[k]) + 1 + s)
+                elif r == "D":
+                    dpos.append(int(m.starts[k]) + 1 + s)
+        w[3] += 7
+        if i % 3 == 0:
+            want.append(0)
+        elif i % 3 == 1:
+            w[upos[len(upos) // 2]] = w[3] - 2  # below the bound, never defined
+            want.append(oracle.E_UNDEFINED_ID)
+        else:
+            w[dpos[len(dpos) // 3]] = w[dpos[len(dpos) // 3 - 1]]
+            want.append(oracle.E_DUPLICATE_ID)
+        mods.append(w)
+    return mods, want
+
+
+@pytest.mark.parametrize("fallback", [True, False])
+def test_second_pass_with_and_without_the_single_pass_walk(fallback):
+    """Modules that need the second pass (undefined-ID search), in a batch
+    that takes the single-pass walk (a name spanning whole tiles: the second
+    pass recovers instruction starts with lane transfer functions) and in
+    one without it (the second pass reads the chain pass's lane starts)."""
+    mods, want = _pass2_modules(31)
+    if fallback:
+        words, mod_off = _batch([[("name", 8200, ("start", 9), None)]], 29)
+        mods = [words] + mods
+        want = [0] + want
+    mod_off = np.concatenate([[0], np.cumsum([w.size for w in mods])]).astype(np.int64)
+    words = np.concatenate(mods)
+    o = oracle.validate(words, mod_off, semantic=True, index=False)
+    assert [int(c) for c in o["code"]] == want, o["code"]
+    compare(words, mod_off, label=f"second pass, fallback={fallback}")
+    compare(words, mod_off, index=False, label=f"second pass, no index, fallback={fallback}")
