@@ -1872,28 +1872,36 @@ __device__ __forceinline__ void main_body(SH& S, const VParams& P) {
           const uint32_t idm = defm | usem;
           bool oob = false;
           if constexpr (kRes) {
-            // (the resolved walk keeps the words in LDS only)
+            // (the resolved walk keeps the words in LDS only; flags gathered
+            // under per-lane branches are integers, not booleans: they stay in
+            // vector registers, with no lane-mask merging at every branch)
+            uint32_t oobm = 0;
 #pragma unroll
-            for (int p = 0; p < kLaneWords; ++p) oob |= ((idm >> p) & 1u) && (S.tw[twx(lrel + p)] - 1u >= bm1);
+            for (int p = 0; p < kLaneWords; ++p)
+              if ((idm >> p) & 1u) oobm |= (S.tw[twx(lrel + p)] - 1u >= bm1) ? 1u : 0u;
+            oob = oobm != 0;
           } else {
 #pragma unroll
             for (int p = 0; p < kLaneWords; ++p) oob |= ((idm >> p) & 1u) && (L.w[p] - 1u >= bm1);
           }
           const int wj = win_of(j0);
           const uint32_t base = wj >= 0 ? win_base(wj) : 0u;
-          bool dup = false;
+          uint32_t dupm = 0;
           uint32_t dm = defm;
+          const uint32_t wlim = wj >= 0 ? 64u * wsz : 0u;
           while (dm) {
             const int p = __builtin_ctz(dm);
             dm &= dm - 1;
             const uint32_t v = S.tw[twx(lrel + p)];
-            if (v - 1u >= bm1) continue;  // out of bound: flagged above
-            if (wj >= 0 && v >= base && v - base < 64u * wsz) {
-              dup |= win_set(wj, base, v);
-            } else {
-              rare |= 1u << p;
+            const uint32_t inb = (v - 1u < bm1) ? 1u : 0u;   // out of bound: flagged above
+            const uint32_t inw = inb & ((v - base < wlim) ? 1u : 0u);
+            rare |= (inb & (inw ^ 1u)) << p;
+            if (inw) {
+              const unsigned long long bit = 1ull << (v & 63u);
+              dupm |= uint32_t((atomicOr(&S.win[wj * wsz + ((v - base) >> 6)], bit) >> (v & 63u)) & 1ull);
             }
           }
+          bool dup = dupm != 0;
           if (oob || dup) atomicOr(&S.modflags[j0], (oob ? kModOOB : 0u) | (dup ? kModDup : 0u));
         } else if (info & kInfoHdrOk) {
           rare = defm | usem;
