@@ -38,6 +38,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "spv_internal.h"
 
 namespace spv {
@@ -1743,39 +1745,46 @@ __device__ __forceinline__ void main_body(SH& S, const VParams& P) {
         dst0 = le.off + pre_local + (lane_in_first ? res_pre : 0u);
         val0 = uint32_t(t0 + lrel - le.off);
       }
-      while (sm) {
-        const int p = __builtin_ctz(sm);
-        sm &= sm - 1;
-        const uint32_t w0 = S.tw[twx(lrel + p)];
-        const uint32_t ee = tbl_lookup(S.tbl, w0 & 0xFFFFu);
-        name_m |= ent_str(ee) << p;
-        if (kSem) {
-          defm |= ((ee >> 24) & 0xFu) << (p + 1);
-          usem |= (ee >> 28) << (p + 1);
-          // module-level rule presence (section "Validation Rules")
-          if (rules_on) {
-            if (rst == 0) rules |= ent_rules(ee);
-            else if (ent_rules(ee)) atomicOr(&S.modflags[lane_mod_at(L, p)], ent_rules(ee) << kModRuleShift);
-          }
-        }
-        if (kIdx) {
-          if (rst == 0) {
-            if (ok0) {
-              P.idx_off[dst0 + k] = val0 + uint32_t(p);
-              P.idx_op[dst0 + k] = uint16_t(w0 & 0xFFFFu);
-            }
-          } else {
-            const int jm = lane_mod_at(L, p);
-            const LEnt& le = S.list[jm];
-            if (le.info & kInfoHdrOk) {
-              const int64_t dst = le.off + rank_local(p) + (in_first(p) ? res_pre : 0u);
-              P.idx_off[dst] = uint32_t(t0 + lrel + p - le.off);
-              P.idx_op[dst] = uint16_t(w0 & 0xFFFFu);
+      // (a wave with no module start in its lanes runs a copy of the loop
+      // without the module-start branches)
+      auto starts_loop = [&](auto plain_t) {
+        constexpr bool kPlain = decltype(plain_t)::value;
+        while (sm) {
+          const int p = __builtin_ctz(sm);
+          sm &= sm - 1;
+          const uint32_t w0 = S.tw[twx(lrel + p)];
+          const uint32_t ee = tbl_lookup(S.tbl, w0 & 0xFFFFu);
+          name_m |= ent_str(ee) << p;
+          if (kSem) {
+            defm |= ((ee >> 24) & 0xFu) << (p + 1);
+            usem |= (ee >> 28) << (p + 1);
+            // module-level rule presence (section "Validation Rules")
+            if (rules_on) {
+              if (kPlain || rst == 0) rules |= ent_rules(ee);
+              else if (ent_rules(ee)) atomicOr(&S.modflags[lane_mod_at(L, p)], ent_rules(ee) << kModRuleShift);
             }
           }
+          if (kIdx) {
+            if (kPlain || rst == 0) {
+              if (ok0) {
+                P.idx_off[dst0 + k] = val0 + uint32_t(p);
+                P.idx_op[dst0 + k] = uint16_t(w0 & 0xFFFFu);
+              }
+            } else {
+              const int jm = lane_mod_at(L, p);
+              const LEnt& le = S.list[jm];
+              if (le.info & kInfoHdrOk) {
+                const int64_t dst = le.off + rank_local(p) + (in_first(p) ? res_pre : 0u);
+                P.idx_off[dst] = uint32_t(t0 + lrel + p - le.off);
+                P.idx_op[dst] = uint16_t(w0 & 0xFFFFu);
+              }
+            }
+          }
+          ++k;
         }
-        ++k;
-      }
+      };
+      if (__ballot(rst != 0) == 0) starts_loop(std::true_type{});
+      else starts_loop(std::false_type{});
       if (kSem) {
         S.spill[tid] = ((defm >> 16) & 0xFu) | (((usem >> 16) & 0xFu) << 4);
         if (rules_on) {
