@@ -664,6 +664,23 @@ __device__ __forceinline__ uint32_t wave_incl_sum(uint32_t x) {
   return x;
 }
 
+// Inclusive segmented wave sum (bit 31 of a value: a segment starts there;
+// the count restarts at it), by the same row shifts and row broadcasts as
+// wave_incl_sum: the combining step is associative, so the same pattern
+// applies, and a lane that receives nothing gets 0, which changes nothing.
+__device__ __forceinline__ uint32_t seg_step(uint32_t x, uint32_t u) {
+  return (x & 0x80000000u) ? x : (x + (u & 0x7FFFFFFFu)) | (u & 0x80000000u);
+}
+__device__ __forceinline__ uint32_t wave_incl_segsum(uint32_t x) {
+  x = seg_step(x, uint32_t(__builtin_amdgcn_update_dpp(0, int(x), 0x111, 0xF, 0xF, false)));
+  x = seg_step(x, uint32_t(__builtin_amdgcn_update_dpp(0, int(x), 0x112, 0xF, 0xF, false)));
+  x = seg_step(x, uint32_t(__builtin_amdgcn_update_dpp(0, int(x), 0x114, 0xF, 0xF, false)));
+  x = seg_step(x, uint32_t(__builtin_amdgcn_update_dpp(0, int(x), 0x118, 0xF, 0xF, false)));
+  x = seg_step(x, uint32_t(__builtin_amdgcn_update_dpp(0, int(x), 0x142, 0xA, 0xF, false)));
+  x = seg_step(x, uint32_t(__builtin_amdgcn_update_dpp(0, int(x), 0x143, 0xC, 0xF, false)));
+  return x;
+}
+
 // Candidate starts of a lane: grammar lookups of all 16 positions (kept in
 // e[] for the result-ID roles), plausibility, long (word count >= 15) and
 // string-operand candidates.
@@ -1153,21 +1170,29 @@ __global__ __launch_bounds__(kBlock, 24 / kWaves) void k_chain(VParams P) {
         errs = 0;
       }
     }
-    // per-module counts: segmented by module starts (as in the main pass)
+    // per-module counts: segmented by module starts (as in the main pass);
+    // a plain sum when no module starts in the tile
     const uint32_t rst = L.rst;
     const uint32_t nst = __popc(starts);
-    uint32_t cval;
-    if (rst) {
-      int last = 31 - __builtin_clz(rst);
-      cval = 0x80000000u | uint32_t(__popc(starts & ~((2u << last) - 1u)));
-    } else {
-      cval = nst;
-    }
-    uint32_t inc = cval;
+    uint32_t inc;
+    if (S.K > 1 || S.list[0].rel >= 0) {
+      uint32_t cval;
+      if (rst) {
+        int last = 31 - __builtin_clz(rst);
+        cval = 0x80000000u | uint32_t(__popc(starts & ~((2u << last) - 1u)));
+      } else {
+        cval = nst;
+      }
+      inc = cval;
+      // (rounds of lane shifts: the row-broadcast form of this scan costs the
+      // pass more registers than it has)
 #pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      uint32_t u = __shfl_up(inc, d);
-      if (lane >= d) inc = (inc & 0x80000000u) ? inc : (inc + (u & 0x7FFFFFFFu)) | (u & 0x80000000u);
+      for (int d = 1; d < 64; d <<= 1) {
+        uint32_t u = __shfl_up(inc, d);
+        if (lane >= d) inc = seg_step(inc, u);
+      }
+    } else {
+      inc = wave_incl_sum(nst);
     }
     const uint32_t excl = wave_shr1(inc, 0u);
     if (lane == 63) S.wcnt[wave] = inc;
@@ -1237,12 +1262,7 @@ __global__ __launch_bounds__(kResolveBlock) void k_resolve(VParams P) {
   const bool rs = real && (v.x & kSumReset);
   const uint32_t val = real ? (rs ? v.w : v.z + c0) : 0u;
   // inclusive segmented scan (bit 31: a module starts in the range)
-  uint32_t inc = (rs ? 0x80000000u : 0u) | val;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    uint32_t u = __shfl_up(inc, d);
-    if (lane >= d) inc = (inc & 0x80000000u) ? inc : (inc + (u & 0x7FFFFFFFu)) | (u & 0x80000000u);
-  }
+  const uint32_t inc = wave_incl_segsum((rs ? 0x80000000u : 0u) | val);
   if (lane == 63) s_wagg[wave] = inc;
   __syncthreads();
   uint32_t wpre = 0, btot = 0;
@@ -1612,12 +1632,7 @@ __device__ __forceinline__ void main_body(SH& S, const VParams& P) {
       } else {
         cval = nst;
       }
-      inc = cval;
-#pragma unroll
-      for (int d = 1; d < 64; d <<= 1) {
-        uint32_t u = __shfl_up(inc, d);
-        if (lane >= d) inc = (inc & 0x80000000u) ? inc : (inc + (u & 0x7FFFFFFFu)) | (u & 0x80000000u);
-      }
+      inc = wave_incl_segsum(cval);
       excl = wave_shr1(inc, 0u);
     } else {
       inc = sinc;
