@@ -209,6 +209,7 @@ struct LEnt {
 };
 constexpr uint32_t kInfoEnd = 8u, kInfoHdrOk = 16u, kInfoSparse = 32u;
 constexpr int kWinWords = 128;  // LDS window of 8192 result IDs per tile
+constexpr uint32_t kNoBound = 0xFFFFFFFFu;  // no load-time bound test (bound - 1 is never this)
 constexpr int kTwTail = 32;     // words past the tile end kept in LDS
 // LDS index of tile position q: one pad word after every 16, so that the 64
 // lanes of a wave, 16 words apart, read a position each from distinct banks
@@ -284,6 +285,10 @@ struct WalkShared {
   uint32_t rl_bits;
   LEnt cache;
   int cache_ok;
+  // bound - 1 of the module that covers this block's next tile and the 16
+  // words after it, when that is the module of its current list entry 0 and
+  // it keeps its result IDs in a bitmap; kNoBound otherwise
+  uint32_t nbm1;
 };
 
 // Build the list of non-empty modules overlapping [t0, t1 + 16] (wave 0).
@@ -1349,6 +1354,9 @@ __device__ __forceinline__ void main_body(SH& S, const VParams& P) {
     S.rl_mod = -1;
     S.rl_bits = 0;
   }
+  if constexpr (kRes) {
+    if (tid == 0) S.nbm1 = kNoBound;
+  }
   // words of the next tile, loaded during the tail of the current one
   uint4 pf[kLaneWords / 4];
   uint32_t pf_tail = 0;  // (threads below kTwTail) a word past the next tile's end
@@ -1402,6 +1410,13 @@ __device__ __forceinline__ void main_body(SH& S, const VParams& P) {
       }
     } else if (L.a + kLaneWords <= P.W) {
       const uint4* src = reinterpret_cast<const uint4*>(P.words + L.a);
+      // resolved walk, a tile inside the module of the block's previous
+      // tile: the bound test of all 16 words as they arrive (bit p: word p
+      // is 0 or at least the bound), kept in the pad word after the lane's
+      // words for the ID checks
+      uint32_t nb = kNoBound;
+      if constexpr (kRes && kSem) nb = S.nbm1;
+      uint32_t badw = 0;
 #pragma unroll
       for (int i = 0; i < kLaneWords / 4; ++i) {
         const uint4 v = src[i];
@@ -1410,6 +1425,11 @@ __device__ __forceinline__ void main_body(SH& S, const VParams& P) {
         L.w[4 * i + 2] = v.z;
         L.w[4 * i + 3] = v.w;
         tw_store4(tid, i, v);
+        badw |= (uint32_t(v.x - 1u >= nb) | (uint32_t(v.y - 1u >= nb) << 1) | (uint32_t(v.z - 1u >= nb) << 2) |
+                 (uint32_t(v.w - 1u >= nb) << 3)) << (4 * i);
+      }
+      if constexpr (kRes && kSem) {
+        if (nb != kNoBound) S.tw[tid * (kLaneWords + 1) + kLaneWords] = badw;
       }
     } else {
 #pragma unroll
@@ -1419,6 +1439,19 @@ __device__ __forceinline__ void main_body(SH& S, const VParams& P) {
       }
     }
     if (tid < kTwTail) S.tw[twx(kTileWords + tid)] = (pf_tile == t) ? pf_tail : ((t1 + tid < P.W) ? P.words[t1 + tid] : 0u);
+    // resolved walk: the chain pass's lane record and the tile's resolved
+    // entry, count prefix and first-lane chain, loaded with the words (the
+    // per-tile values through scalar loads)
+    uint32_t h_rec = 0, h_pre = 0, h_E = 0, h_m0 = 0;
+    if constexpr (kRes) {
+      h_rec = P.lst[t * kBlock + tid];
+      const uint32_t tl = __builtin_amdgcn_readfirstlane(uint32_t(t));
+      const uint32_t th = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(t) >> 32));
+      const long long tu = (long long)(((uint64_t)th << 32) | tl);
+      h_pre = P.tres[2 * tu + 1];
+      h_E = P.tres[2 * tu];
+      h_m0 = P.tsum[4 * tu + 1];
+    }
     if (wave == 0) build_list(S, P, t, t0, t1);
     if (tid < kListMax) {
       S.modflags[tid] = 0;
@@ -1471,13 +1504,13 @@ __device__ __forceinline__ void main_body(SH& S, const VParams& P) {
     if constexpr (kRes) {
       // starts and parse-error nodes from the chain pass; the first lane adds
       // the part of its candidate chain that its resolved entry reaches
-      const uint32_t rec = P.lst[t * kBlock + tid];
-      res_pre = P.tres[2 * t + 1];
+      const uint32_t rec = h_rec;
+      res_pre = h_pre;
       starts = rec & 0xFFFFu;
       errs = rec >> 16;
       if (tid == 0) {
-        const uint32_t Et = P.tres[2 * t];
-        const uint32_t m0 = P.tsum[4 * t + 1];
+        const uint32_t Et = h_E;
+        const uint32_t m0 = h_m0;
         const uint32_t h0 = L.hdr ? uint32_t(__builtin_ctz(L.hdr)) : 16u;
         if (Et < 14u && Et < h0) {
           if ((m0 >> Et) & 1u) {
@@ -1899,11 +1932,16 @@ __device__ __forceinline__ void main_body(SH& S, const VParams& P) {
             // (the resolved walk keeps the words in LDS only; flags gathered
             // under per-lane branches are integers, not booleans: they stay in
             // vector registers, with no lane-mask merging at every branch)
-            uint32_t oobm = 0;
+            if (S.nbm1 != kNoBound) {
+              // (the bound test of the words, taken at their load)
+              oob = (idm & S.tw[tid * (kLaneWords + 1) + kLaneWords]) != 0;
+            } else {
+              uint32_t oobm = 0;
 #pragma unroll
-            for (int p = 0; p < kLaneWords; ++p)
-              if ((idm >> p) & 1u) oobm |= (S.tw[twx(lrel + p)] - 1u >= bm1) ? 1u : 0u;
-            oob = oobm != 0;
+              for (int p = 0; p < kLaneWords; ++p)
+                if ((idm >> p) & 1u) oobm |= (S.tw[twx(lrel + p)] - 1u >= bm1) ? 1u : 0u;
+              oob = oobm != 0;
+            }
           } else {
 #pragma unroll
             for (int p = 0; p < kLaneWords; ++p) oob |= ((idm >> p) & 1u) && (L.w[p] - 1u >= bm1);
@@ -2118,6 +2156,22 @@ __device__ __forceinline__ void main_body(SH& S, const VParams& P) {
       }
     }
     } while (false);
+    // the bound for the next tile's load-time test (list entry 0 is read
+    // before the next tile rebuilds the list, behind the loop's barrier)
+    if constexpr (kRes && kSem) {
+      if (tid == 0) {
+        const long long tn = t + gridDim.x;
+        uint32_t nb = kNoBound;
+        if (tn < P.n_tiles) {
+          const int64_t t0n = tn * kTileWords;
+          const int64_t t1n = (t0n + kTileWords < P.W) ? t0n + kTileWords : P.W;
+          const LEnt& c = S.list[0];
+          if (c.mod >= 0 && c.off <= t0n && c.end > t1n + 16 && (c.info & kInfoHdrOk) && !(c.info & kInfoSparse))
+            nb = c.bound ? c.bound - 1u : 0u;
+        }
+        S.nbm1 = nb;
+      }
+    }
     if constexpr (!kRes) {
       if (go_serial) {
         if (tid == kBlock - 1) S.tnext = claim_tn;
