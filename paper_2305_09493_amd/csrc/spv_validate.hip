@@ -1207,6 +1207,21 @@ __global__ __launch_bounds__(kBlock, 24 / kWaves) void k_chain(VParams P) {
       if (tid == 0) sum[0] = kSumFallback;
       continue;
     }
+    if (!(S.K > 1 || S.list[0].rel >= 0)) {
+      // no module starts in the tile: every start belongs to the module open
+      // at its start, so the count of those starts is the tile total, and
+      // no further barrier is needed (the next tile begins with one)
+      P.lst[t * kBlock + tid] = starts | (errs << 16);
+      if (tid == 0) {
+        uint32_t tot = 0;
+        for (int w = 0; w < kWaves; ++w) tot += S.wcnt[w];
+        sum[0] = X;
+        sum[1] = mask0;
+        sum[2] = tot;
+        sum[3] = tot;
+      }
+      continue;
+    }
     uint32_t wpre = 0, tot = 0;
     for (int w = 0; w < kWaves; ++w) {
       uint32_t v = S.wcnt[w];
