@@ -582,20 +582,23 @@ __global__ __launch_bounds__(kRecThreads) void k_txt_insert(TParams P) {
     const uint32_t nw = (P.words[e.y] >> 16) - 2;  // the name's words
     const uint32_t* w = P.words + e.y + 2;
     uint32_t len = 0;
-    bool ok = true;
+    // (all four bytes of a word tested, the ones past the string masked; the
+    // flag an integer: no per-byte branches or lane-mask merging)
+    uint32_t bad = 0;
 #pragma unroll 4
     for (uint32_t k = 0; k < nw; ++k) {
       const uint32_t x = w[k];
       const uint32_t nb = k + 1 < nw ? 4u : last_word_bytes(x);
-      for (uint32_t q = 0; q < nb; ++q) {
+#pragma unroll
+      for (uint32_t q = 0; q < 4; ++q) {
         const uint32_t c = (x >> (8 * q)) & 0xFFu;
-        const bool alpha = (c >= 'a' && c <= 'z') || (c >= 'A' && c <= 'Z') || c == '_';
-        const bool digit = c >= '0' && c <= '9';
-        if (!(alpha || (digit && (k | q) != 0))) ok = false;
+        const uint32_t alpha = (c - 'a' < 26u || c - 'A' < 26u || c == '_') ? 1u : 0u;
+        const uint32_t digit = (c - '0' < 10u && (k | q) != 0u) ? 1u : 0u;
+        bad |= (q < nb && (alpha | digit) == 0u) ? 1u : 0u;
       }
       len += nb;
     }
-    const unsigned long long val = ((unsigned long long)e.y << 32) | (ok ? len : 0u);
+    const unsigned long long val = ((unsigned long long)e.y << 32) | (bad ? 0u : len);
     const unsigned long long key = ((unsigned long long)e.x << 32) | P.words[e.y + 1];
     const unsigned long long mixed = txt_mix(key);
     const uint32_t fb = txt_fbit(mixed);
