@@ -265,7 +265,18 @@ __device__ __forceinline__ void put_id(S& s, const TParams& P, bool hl, IdName n
   if (nm.len) {
     if constexpr (S::kWrite) {
       const uint32_t* w = P.words + nm.pos + 2;  // OpName: first word, target, then the name
-      for (uint32_t i = 0; i < nm.len; ++i) s.put((w[i >> 2] >> (8 * (i & 3))) & 0xFFu);
+      // (one load per word of the name)
+      for (uint32_t j = 0; 4 * j < nm.len; ++j) {
+        const uint32_t x = w[j];
+        if (4 * j + 4 <= nm.len) {
+          s.put(x & 0xFFu);
+          s.put((x >> 8) & 0xFFu);
+          s.put((x >> 16) & 0xFFu);
+          s.put(x >> 24);
+        } else {
+          for (uint32_t q = 0; 4 * j + q < nm.len; ++q) s.put((x >> (8 * q)) & 0xFFu);
+        }
+      }
     } else {
       s.o += nm.len;
     }
@@ -321,6 +332,15 @@ __device__ __forceinline__ void put_string(S& s, const uint32_t* w, uint32_t nw)
     for (uint32_t i = 0; i < nw; ++i) {
       const uint32_t x = w[i];
       const uint32_t nb = i + 1 < nw ? 4u : last_word_bytes(x);
+      const uint32_t esc = zero_bytes(x ^ 0x22222222u) | zero_bytes(x ^ 0x5C5C5C5Cu);
+      if (nb == 4u && esc == 0u) {
+        // (a whole word with nothing to escape: four bytes, no per-byte branch)
+        s.put(x & 0xFFu);
+        s.put((x >> 8) & 0xFFu);
+        s.put((x >> 16) & 0xFFu);
+        s.put(x >> 24);
+        continue;
+      }
       for (uint32_t q = 0; q < nb; ++q) {
         const uint32_t c = (x >> (8 * q)) & 0xFFu;
         if (c == '"' || c == '\\') s.put('\\');
