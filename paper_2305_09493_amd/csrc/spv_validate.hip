@@ -1970,7 +1970,7 @@ __device__ __forceinline__ void main_body(SH& S, const VParams& P) {
             const int p = __builtin_ctz(dm);
             dm &= dm - 1;
             const uint32_t v = S.tw[twx(lrel + p)];
-            const uint32_t inb = (v - 1u < bm1) ? 1u : 0u;   // out of bound: flagged above
+            const uint32_t inb = (v - 1u < bm1) ? 1u : 0u;  // in bound (the others were flagged above)
             const uint32_t inw = inb & ((v - base < wlim) ? 1u : 0u);
             rare |= (inb & (inw ^ 1u)) << p;
             if (inw) {
