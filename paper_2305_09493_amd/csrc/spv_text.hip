@@ -51,6 +51,7 @@ namespace {
 constexpr uint64_t kInstMask = (1ull << 29) - 1;  // low bits of the module scan: instructions
 constexpr int kHdrShift = 29;                      // high bits: header bytes
 constexpr int kStageBytes = 30720;                 // LDS staging per slice of 256 lines
+constexpr uint32_t kLenBits = 28;  // a line's length (< 2^20: at most 4 names and a string of 65533 words); above it, its name bits
 
 // Every fixed token the lines print, concatenated: opcode names (ids 0..12),
 // capabilities 0..12, 22, 39 (13..27), addressing models 0..2 (28..30), memory
@@ -376,9 +377,12 @@ __device__ __forceinline__ InstWords load_inst(const TParams& P, int64_t pos) {
 }
 
 // The text line of the instruction at word position pos of module m.
-template <class S>
+// nmask: bit k set when operand k's ID has a name.  The length pass (kFind)
+// looks every ID up and sets the bits; the scatter looks up only the IDs
+// whose bit is set (the others print as numbers).
+template <bool kFind, class S>
 __device__ __forceinline__ void txt_line(const TParams& P, unsigned long long nslots, uint32_t m, int64_t pos,
-                                         const InstWords& iw, S& s) {
+                                         const InstWords& iw, S& s, uint32_t& nmask) {
   const uint32_t w0 = iw.w[0], op = w0 & 0xFFFFu;
   const TxtOp d = txt_op(op);
   const uint32_t opt = P.options;
@@ -387,16 +391,23 @@ __device__ __forceinline__ void txt_line(const TParams& P, unsigned long long ns
 #pragma unroll
   for (uint32_t k = 0; k < 4; ++k) v[k] = k < d.nfix ? iw.w[1 + k] : 0u;
   bool has_res = false;
-  uint32_t rv = 0;
+  uint32_t rv = 0, rk = 0;
 #pragma unroll
   for (uint32_t k = 0; k < 4; ++k)
     if (((d.roles >> (2 * k)) & 3u) == 2u) {
       has_res = true;
       rv = v[k];
+      rk = k;
     }
+  auto name_of = [&](uint32_t k, uint32_t id) -> IdName {
+    if (!kFind && !((nmask >> k) & 1u)) return IdName{0u, 0u};
+    const IdName nm = txt_name(P, nslots, m, id);
+    if (kFind && nm.len) nmask |= 1u << k;
+    return nm;
+  };
   if ((opt & kTxtGroup) && (op == 54u || op == 248u)) s.put('\n');
   IdName rn{0u, 0u};
-  if (has_res && names) rn = txt_name(P, nslots, m, rv);
+  if (has_res && names) rn = name_of(rk, rv);
   if (!(opt & kTxtNoIndent)) {
     const uint32_t width = has_res ? 4u + (rn.len ? rn.len : ndigits(rv)) : 0u;  // "%" token " = "
     for (uint32_t c = width; c < 15u; ++c) s.put(' ');
@@ -417,7 +428,7 @@ __device__ __forceinline__ void txt_line(const TParams& P, unsigned long long ns
     if (role == 2u) continue;
     s.put(' ');
     if (role == 1u) {
-      const IdName nm = names ? txt_name(P, nslots, m, v[k]) : IdName{0u, 0u};
+      const IdName nm = names ? name_of(k, v[k]) : IdName{0u, 0u};
       put_id(s, P, hl, nm, v[k]);
     } else {
       put_lit(s, hl, (d.lits >> (3 * k)) & 7u, v[k]);
@@ -669,8 +680,9 @@ __global__ __launch_bounds__(kRecThreads) void k_txt_lens(TParams P) {
       const int64_t r = b * kScanBlock + int64_t(k) * kRecThreads + tid;
       if (pk[k] >= 0) {
         CountSink c{0, nullptr};
-        txt_line(P, ns, uint32_t(mk[k]), pk[k], iw[k], c);
-        P.lens[r] = c.o;
+        uint32_t nmask = 0;
+        txt_line<true>(P, ns, uint32_t(mk[k]), pk[k], iw[k], c, nmask);
+        P.lens[r] = c.o | (nmask << kLenBits);  // (the scatter reads the name bits back)
         P.lpos[r] = uint32_t(pk[k]);
         sum += c.o;
       }
@@ -723,7 +735,7 @@ __global__ __launch_bounds__(kRecThreads, 5) void k_txt_scatter(TParams P) {
 #pragma unroll
     for (int k = 0; k < kScanPerThread; ++k) {
       const int64_t r = b * kScanBlock + int64_t(k) * kRecThreads + tid;
-      Lk[k] = r < N ? P.lens[r] : 0u;
+      Lk[k] = r < N ? P.lens[r] : 0u;  // length | name bits << kLenBits
       pk[k] = r < N ? P.lpos[r] : 0u;
     }
 #pragma unroll
@@ -732,7 +744,8 @@ __global__ __launch_bounds__(kRecThreads, 5) void k_txt_scatter(TParams P) {
       if (r0 >= N) break;  // (uniform over the block)
       const int64_t r = r0 + tid;
       const bool valid = r < N;
-      const uint32_t L = Lk[k];
+      const uint32_t L = Lk[k] & ((1u << kLenBits) - 1u);
+      uint32_t nmask = Lk[k] >> kLenBits;
       InstWords iwk;
       if (valid) iwk = load_inst(P, int64_t(pk[k]));
       int64_t m = 0;
@@ -765,10 +778,10 @@ __global__ __launch_bounds__(kRecThreads, 5) void k_txt_scatter(TParams P) {
       if (valid) {
         if (staged) {
           LdsSink sk{stage, uint32_t(g - G0a), s_tok};
-          txt_line(P, ns, uint32_t(m), int64_t(pk[k]), iwk, sk);
+          txt_line<false>(P, ns, uint32_t(m), int64_t(pk[k]), iwk, sk, nmask);
         } else {
           GlobalSink sk{P.text, g, P.text_cap, 0u, s_tok};
-          txt_line(P, ns, uint32_t(m), int64_t(pk[k]), iwk, sk);
+          txt_line<false>(P, ns, uint32_t(m), int64_t(pk[k]), iwk, sk, nmask);
         }
       }
       __syncthreads();
