@@ -212,3 +212,53 @@ def test_autotuner_picks_a_candidate_and_keeps_parity(tmp_path, monkeypatch):
         assert e["encode_block"] in (256, 1024)
     finally:
         ctx.set_tuning(blocks_per_cu=old[0], encode_block=old[1])
+
+
+def _id_word(m, want_role, tile_min, lane_pos=None, last_lane=False):
+    """Position of an ID word of role want_role ('U' or 'D') in tile >= tile_min
+    (optionally at lane position lane_pos, or in the tile's last lane)."""
+    for k in range(spvgen.N_PROLOGUE, m.n_inst):
+        for s, r in enumerate(spvgen.ROLES[m.kind[k]]):
+            if r != want_role:
+                continue
+            pos = int(m.starts[k]) + 1 + s
+            if pos // 4096 < tile_min:
+                continue
+            if lane_pos is not None and pos % 16 != lane_pos:
+                continue
+            if last_lane and pos % 4096 < 4080:
+                continue
+            return pos
+    raise AssertionError("no such ID word")
+
+
+@pytest.mark.parametrize("case", ["use", "def", "use at lane start", "use in last lane", "zero"])
+def test_load_time_bound_test_on_later_tiles(case):
+    """With one walk block per CU, a block's later tiles lie inside the module
+    of its previous tile, where the walk tests the ID words' bound as they
+    load: an out-of-bound use or result ID (or ID 0) placed there, also at a
+    lane's first words (IDs of the previous lane's last instruction) and in
+    a tile's last lane, is found as on the oracle."""
+    import paper_2305_09493_amd as spv
+    m = spvgen.gen_module(80, 400_000)
+    w = m.words.copy()
+    bound = int(w[3])
+    if case == "use":
+        w[_id_word(m, "U", 300)] = bound + 5
+    elif case == "def":
+        w[_id_word(m, "D", 300)] = bound
+    elif case == "use at lane start":
+        w[_id_word(m, "U", 300, lane_pos=1)] = 0xFFFFFFF0
+    elif case == "use in last lane":
+        w[_id_word(m, "U", 300, last_lane=True)] = bound + 1
+    else:
+        w[_id_word(m, "U", 300)] = 0
+    o = oracle.validate(w, np.array([0, w.size], np.int64), semantic=True, index=False)
+    assert int(o["code"][0]) == oracle.E_ID_OUT_OF_BOUND, o["code"]
+    ctx = spv.context()
+    old = ctx.get_grids()
+    try:
+        ctx.set_grids(1, 1)
+        compare(w, [0, w.size], label=f"load-time bound test, {case}")
+    finally:
+        ctx.set_grids(*old)
