@@ -232,7 +232,9 @@ __global__ __launch_bounds__(kEncThreads) void k_enc_scan(EParams P) {
 // trips, and staging adds barriers without removing any.
 constexpr int kEncChunk = 1;
 
-__global__ __launch_bounds__(kEncThreads) void k_enc_scatter(EParams P) {
+// (six waves per SIMD: 80 registers; more resident waves hide more of the
+// scatter's memory round trips, eight spill)
+__global__ __launch_bounds__(kEncThreads, 6) void k_enc_scatter(EParams P) {
   __shared__ uint16_t tbl[257];
   __shared__ uint32_t s_w[kEncChunk][kEncThreads / 64];
   __shared__ int64_t s_off[kEncThreads + 1];  // rec_mod_off[m0 .. m0 + 256], past M: no start
