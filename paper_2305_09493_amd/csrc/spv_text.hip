@@ -647,7 +647,9 @@ __global__ __launch_bounds__(kRecThreads) void k_txt_insert(TParams P) {
 }
 
 // Line lengths, and the total of every block of 1024 lines.
-__global__ __launch_bounds__(kRecThreads) void k_txt_lens(TParams P) {
+// (eight waves per SIMD, 64 registers: the pass waits on dependent loads, and
+// more resident waves hide more of them)
+__global__ __launch_bounds__(kRecThreads, 8) void k_txt_lens(TParams P) {
   __shared__ int64_t s_mb[2];
   __shared__ unsigned long long s_w[kRecThreads / 64];
   if (P.ctrl[2]) return;
